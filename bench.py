@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of dtANS-fused sparse matrix-vector multiplication on one MI355X.
+
+Default workload: the 27-point stencil on a 128^3 grid in FP64 (2,097,152
+rows, 55,742,968 nonzeros, 216 distinct values), y = A x, synthetic seeded
+data.  A step is one multiplication: decode of every compressed stream fused
+with the multiply-accumulate and the write of y.
+
+Inputs are resident in device memory before the timed region.  The timed loop
+cycles through several copies of the encoded matrix and of x / y so that
+consecutive steps never find their data in the 256 MB memory-side cache
+(MALL): every step streams its compressed matrix from HBM.  The same
+multiplication on a single copy, back to back ("warm"), and the plain HIP CSR
+kernel on the same GPU are reported alongside, as is the CPU oracle on the
+host cores.
+
+Prints one JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMV GFLOP/s + compressed HBM GB/s, dtANS-CSR vs plain CSR, same MI355X"
+HBM_PEAK_GBPS = 8000.0
+MALL_BYTES = 256 << 20
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import workloads
+
+    if name == "stencil":
+        rp, ci, v = workloads.stencil27(128)
+        return dict(name="stencil27 128^3 fp64 spmv", rp=rp, ci=ci, v=v, n=128 ** 3, k=1, cfg=2)
+    if name == "band":
+        rp, ci, v = workloads.band()
+        return dict(name="band 4096x4096 16/row fp64 spmv", rp=rp, ci=ci, v=v, n=4096, k=1, cfg=1)
+    if name == "rmat":
+        rp, ci, v = workloads.rmat(22)
+        return dict(name="rmat scale22 ef16 fp32 spmv", rp=rp, ci=ci, v=v, n=1 << 22, k=1, cfg=3)
+    if name.startswith("pruned"):
+        k = int(name[len("pruned"):] or 1)
+        rp, ci, v = workloads.pruned_weight()
+        return dict(name="pruned 11008x4096 bf16-valued fp32 spmm k=%d" % k, rp=rp, ci=ci, v=v,
+                    n=4096, k=k, cfg=4)
+    raise SystemExit("unknown workload " + name)
+
+
+def time_steps(torch, fn, steps, warmup):
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        fn(i)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def cpu_baseline(W, seconds):
+    """The oracle (plain FP64 CSR SpMV in C, single thread) on the same
+    matrix, repeated for about `seconds`."""
+    import oracle
+
+    rp, ci, v = W["rp"], W["ci"], W["v"]
+    x = np.random.default_rng(0).uniform(-1, 1, W["n"])
+    if W["k"] == 1:
+        fn = lambda: oracle.spmv(rp, ci, v, x)  # noqa: E731
+        flops = 2.0 * len(ci)
+    else:
+        X = np.random.default_rng(0).uniform(-1, 1, (W["n"], W["k"]))
+        fn = lambda: oracle.spmm(rp, ci, v, X)  # noqa: E731
+        flops = 2.0 * len(ci) * W["k"]
+    fn()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle FP64 CSR %s over the whole matrix, %d repetitions in %.1f s"
+                      % ("SpMV" if W["k"] == 1 else "SpMM", reps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="stencil")
+    ap.add_argument("--layout", default="auto")
+    ap.add_argument("--lane-nnz", type=int, default=0)
+    ap.add_argument("--waves-per-wg", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-csr", action="store_true")
+    ap.add_argument("--traffic", default=None, help="JSON with measured HBM bytes per launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2603_01915_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    log("generating workload %s" % args.workload)
+    W = make_workload(args.workload)
+    rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
+    m, nnz = len(rp) - 1, len(ci)
+    is64 = v.dtype == np.float64
+    vb = 8 if is64 else 4
+    tdt = torch.float64 if is64 else torch.float32
+    log("encoding %d x %d, %d nonzeros" % (m, n, nnz))
+    t0 = time.perf_counter()
+    A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
+                           waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu)
+    enc_s = time.perf_counter() - t0
+    info = A0.info()
+    log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
+                                                                 info["total_bytes"], info["csr_bytes"]))
+    vec_bytes = (n + m) * k * vb
+    per_copy = info["total_bytes"] + vec_bytes
+    copies = args.copies or max(1, math.ceil(2 * MALL_BYTES / per_copy))
+    mats = [A0]
+    if copies > 1:  # further copies come from the saved container (load verifies it)
+        import tempfile
+
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "a.dtans")
+            A0.save(path)
+            for _ in range(copies - 1):
+                B = P.Matrix.load(path)
+                B.set_launch(args.waves_per_wg, args.wg_per_cu)
+                mats.append(B)
+    for A in mats:
+        A.to_device()
+    gen = torch.Generator(device="cuda").manual_seed(2000 + W["cfg"])
+    shape_x = (n,) if k == 1 else (n, k)
+    shape_y = (m,) if k == 1 else (m, k)
+    xs = [torch.rand(shape_x, dtype=tdt, device="cuda", generator=gen) * 2 - 1 for _ in range(copies)]
+    ys = [torch.empty(shape_y, dtype=tdt, device="cuda") for _ in range(copies)]
+
+    def step(i):
+        j = i % copies
+        if k == 1:
+            mats[j].spmv(xs[j], ys[j])
+        else:
+            mats[j].spmm(xs[j], ys[j])
+
+    log("timing %d steps over %d copies" % (args.steps, copies))
+    ms, wall = time_steps(torch, step, args.steps, args.warmup)
+    warm_ms, _ = time_steps(torch, lambda i: step(0), args.steps, args.warmup)
+    flops = 2.0 * nnz * k
+    alg_bytes = info["total_bytes"] + vec_bytes
+    gflops = flops / (ms * 1e-3) / 1e9
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC, "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if is64 else "f32", "data": "synthetic (seeded generator)",
+        "config": {"workload": W["name"], "rows": m, "cols": n, "nnz": nnz, "k": k,
+                   "layout": {1: "row", 2: "nnz"}[info["layout"]], "lane_nnz": info["lane_nnz"],
+                   "waves_per_wg": info["waves_per_wg"], "copies_rotated": copies},
+        "compressed_GBps": round(achieved, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "compression": {"dtans_bytes": info["total_bytes"], "stream_bytes": info["stream_bytes"],
+                        "csr_bytes": info["csr_bytes"], "coo_bytes": info["coo_bytes"],
+                        "sell32_bytes": info["sell_bytes"], "bits_per_nnz": round(info["bits_per_nnz"], 3),
+                        "ratio_vs_csr": round(info["csr_bytes"] / info["total_bytes"], 3),
+                        "ratio_vs_smallest": round(min(info["csr_bytes"], info["coo_bytes"],
+                                                       info["sell_bytes"]) / info["total_bytes"], 3),
+                        "escaped_deltas": info["esc_delta"], "escaped_values": info["esc_value"]},
+        "warm": {"ms": round(warm_ms, 6), "GFLOP/s": round(flops / (warm_ms * 1e-3) / 1e9, 3),
+                 "GB/s": round(alg_bytes / (warm_ms * 1e-3) / 1e9, 2)},
+        "encode_seconds": round(enc_s, 2),
+    }
+    if args.traffic:
+        with open(args.traffic) as f:
+            res["roofline"]["traffic"] = json.load(f).get("bytes_per_launch")
+    if not args.no_csr:
+        log("plain CSR baseline")
+        B = P.CsrBaseline(rp, ci, v, n)
+        csr_copies = max(1, math.ceil(2 * MALL_BYTES / (B.bytes + vec_bytes)))
+        Bs = [B] + [P.CsrBaseline(rp, ci, v, n) for _ in range(csr_copies - 1)]
+        bx = [torch.rand(shape_x, dtype=tdt, device="cuda", generator=gen) * 2 - 1 for _ in range(csr_copies)]
+        by = [torch.empty(shape_y, dtype=tdt, device="cuda") for _ in range(csr_copies)]
+
+        def cstep(i):
+            j = i % csr_copies
+            if k == 1:
+                Bs[j].spmv(bx[j], by[j])
+            else:
+                Bs[j].spmm(bx[j], by[j])
+
+        cms, _ = time_steps(torch, cstep, args.steps, args.warmup)
+        cb = B.bytes + vec_bytes
+        res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),
+                               "GB/s": round(cb / (cms * 1e-3) / 1e9, 2),
+                               "frac": round(cb / (cms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                               "copies_rotated": csr_copies}
+        res["speedup_vs_csr"] = round(cms / ms, 3)
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

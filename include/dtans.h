@@ -1,0 +1,207 @@
+/*
+ * dtans.h - C ABI of libdtans: sparse matrix-vector multiplication fused with
+ * dtANS entropy decoding on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of "Fast Entropy Decoding for Sparse MVM on GPUs"
+ * (Schaetzle, Pegolotti, Pueschel, 2026): a CSR matrix is entropy coded once
+ * on the host (column deltas per row, Sec. IV-A; interleaved delta/value
+ * symbols and wave-interleaved 32-bit word streams, Sec. IV-B; coding tables
+ * of K = 4096 slots with multiplicity cap M = 256, Sec. IV-C; two-pass
+ * encoder, Sec. IV-E), and every multiplication decodes the streams on the
+ * fly while multiplying (Sec. II-B, Alg. 3), so the uncompressed matrix never
+ * exists in device memory.
+ *
+ * Conventions for every entry point:
+ *   - Return value: DTANS_OK (0) or a positive error code; a thread-local
+ *     message for the last error is available from dtans_last_error().
+ *   - "host" pointers point to CPU memory and are only read during the call
+ *     (borrowed).  "device" pointers are HIP device allocations owned by the
+ *     caller (e.g. torch tensor data_ptr()); the library never frees them.
+ *   - Device calls are asynchronous on the caller's HIP stream (NULL = the
+ *     null stream) and never synchronize implicitly.  Arguments are validated
+ *     on the host before anything is launched; a launch failure returns
+ *     DTANS_EHIP.
+ *   - Vectors have the matrix's value type (float for DTANS_F32, double for
+ *     DTANS_F64); alpha/beta are passed as double and rounded to that type.
+ *     beta == 0 means the output is not read (it may hold NaN).
+ *   - Indices are 32-bit (Sec. V: int32 CSR); nnz, rows and columns must be
+ *     below 2^31.
+ *   - A handle is used by one thread at a time; calls on different handles
+ *     may run concurrently.
+ */
+#ifndef DTANS_H
+#define DTANS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dtans_status;
+enum {
+    DTANS_OK = 0,
+    DTANS_EINVAL = 1,      /* bad argument (null pointer, size, dtype, option) */
+    DTANS_EUNSORTED = 2,   /* columns not ascending within a row */
+    DTANS_ERANGE = 3,      /* nnz, row or column count or index >= 2^31 */
+    DTANS_ENOMEM = 4,      /* host or device allocation failed */
+    DTANS_EHIP = 5,        /* HIP runtime error (message has the HIP error) */
+    DTANS_ECORRUPT = 6,    /* container fails its checksum or consistency check */
+    DTANS_EUNSUPPORTED = 7,/* valid request the library does not implement */
+    DTANS_EIO = 8          /* file could not be read or written */
+};
+
+typedef enum { DTANS_F32 = 1, DTANS_F64 = 2 } dtans_dtype;
+
+/* Stream layouts.  ROW: lane = one row, wave = 64 consecutive rows (the
+ * paper's slice-to-warp mapping, Sec. II-B/IV-B, with 64-lane wavefronts).
+ * NNZ: lane = lane_nnz consecutive nonzeros in row-major order, so every lane
+ * does the same work whatever the row lengths; rows that cross lanes are
+ * summed by a fix-up pass.  AUTO lets the encoder choose. */
+typedef enum { DTANS_LAYOUT_AUTO = 0, DTANS_LAYOUT_ROW = 1, DTANS_LAYOUT_NNZ = 2 } dtans_layout;
+
+typedef struct {
+    int32_t layout;        /* dtans_layout */
+    int32_t lane_nnz;      /* NNZ layout: nonzeros per lane, multiple of 4; 0 = auto */
+    int32_t waves_per_wg;  /* kernel launch: wavefronts per workgroup (1..16); 0 = auto */
+    int32_t wg_per_cu;     /* kernel launch: persistent workgroups per CU; 0 = auto */
+    int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
+    int32_t reserved;
+    uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
+} dtans_encode_opts;
+
+/* Sizes and statistics of an encoded matrix. */
+typedef struct {
+    int64_t m, n, nnz;
+    int32_t dtype, layout, lane_nnz, waves_per_wg;
+    int64_t num_lanes, num_waves;
+    int64_t words, esc_delta, esc_value;   /* counts of 32-bit words / raw symbols */
+    int64_t table_bytes;                   /* device coding tables (K slots x 16 or 12 B) */
+    int64_t stream_bytes;                  /* words + escapes */
+    int64_t index_bytes;                   /* row pointers, per-wave offsets, lane metadata */
+    int64_t total_bytes;                   /* everything one multiplication reads besides x, y */
+    int64_t csr_bytes, coo_bytes, sell_bytes; /* same matrix in CSR / COO / SELL-64 */
+    int32_t delta_symbols, value_symbols;  /* table symbols per alphabet (escape excluded) */
+    double delta_entropy, value_entropy;   /* H of the delta / value distribution, bits (Eq. 1) */
+    double delta_cross_entropy, value_cross_entropy; /* H(P, P') of the fitted tables (Eq. 2) */
+    double bits_per_nnz;                   /* 8 * stream_bytes / nnz */
+} dtans_info;
+
+typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */
+typedef struct dtans_batch dtans_batch;   /* references matrices, does not own them */
+
+/* Library version string. */
+const char *dtans_version(void);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *dtans_last_error(void);
+
+/* Fill *opts with defaults (layout AUTO, everything else auto, seed 1). */
+void dtans_default_opts(dtans_encode_opts *opts);
+
+/*
+ * Encode a CSR matrix (Sec. II-A, IV-A..F).  Host pointers: row_ptr (m+1),
+ * col_idx (nnz), vals (nnz floats or doubles).  Columns ascending within each
+ * row (duplicates allowed) unless opts->sort_rows.  opts may be NULL.
+ * On success *out owns a new handle (release with dtans_destroy).
+ */
+dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                              const dtans_encode_opts *opts, dtans_matrix **out);
+
+/* Write / read the container file (Sec. II-A: the encoded matrix can be kept
+ * for repeated decoding).  dtans_load checks the checksum and structure and
+ * verifies by a full host decode before returning a handle. */
+dtans_status dtans_save(const dtans_matrix *mat, const char *path);
+dtans_status dtans_load(const char *path, dtans_matrix **out);
+
+/* Copy the encoded matrix to the current HIP device (idempotent; the copy is
+ * enqueued on `stream`).  The device multiplication calls upload implicitly. */
+dtans_status dtans_to_device(dtans_matrix *mat, void *stream);
+
+/* Sizes, entropies and launch configuration. */
+dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *out);
+
+/* Change the launch configuration of an encoded matrix (0 keeps the value). */
+dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu);
+
+/*
+ * y = alpha * A x + beta * y (Sec. III-A; the paper's y = Ax is alpha=1,
+ * beta=0).  Device pointers: x (n values), y (m values).
+ */
+dtans_status dtans_spmv(dtans_matrix *mat, const void *x, void *y, double alpha, double beta,
+                        void *stream);
+
+/*
+ * Multi-vector product Y = alpha * A X + beta * Y, decoding each stream once
+ * for all k right-hand sides.  X is n x k row-major with leading dimension
+ * ldx >= k; Y is m x k row-major with ldy >= k (device pointers).
+ */
+dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
+                        int64_t ldy, double alpha, double beta, void *stream);
+
+/*
+ * Transposed product dX = alpha * A^T dY + beta * dX by decode-and-scatter of
+ * the same streams (atomic adds: the summation order is not deterministic).
+ * dY is m x k (lddy >= k), dX is n x k (lddx >= k), device pointers.
+ */
+dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t lddy, void *dX,
+                          int64_t lddx, double alpha, double beta, void *stream);
+
+/*
+ * Decode the whole matrix back to CSR on the device (verification; the
+ * result is bit-identical to the encoded CSR).  Device pointers: row_ptr
+ * (m+1 int32), col_idx (nnz int32), vals (nnz values).
+ */
+dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_idx, void *vals,
+                              void *stream);
+
+/*
+ * Many matrices in one persistent launch.  All matrices share the dtype.
+ * xs[i] / ys[i] are device pointers for matrix i (host array of pointers).
+ */
+dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_batch **out);
+dtans_status dtans_batch_spmv(dtans_batch *batch, const void *const *xs, void *const *ys,
+                              double alpha, double beta, void *stream);
+void dtans_batch_destroy(dtans_batch *batch);
+
+/*
+ * Plain CSR baseline on the same GPU (the uncompressed comparison format of
+ * Sec. V).  dtans_csr_create copies host CSR arrays (row_ptr m+1, col_idx
+ * nnz, vals nnz) to the current device and plans the launch; variant:
+ * 0 = automatic, 1 = a group of lanes per row sized by the mean row length,
+ * 2 = equal nonzeros per lane with a fix-up for rows that cross lanes.
+ * dtans_csr_spmv / dtans_csr_spmm compute y = alpha*A*x + beta*y and
+ * Y = alpha*A*X + beta*Y with the same conventions as dtans_spmv / _spmm.
+ */
+typedef struct dtans_csr dtans_csr;
+dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                              int32_t variant, dtans_csr **out);
+dtans_status dtans_csr_spmv(dtans_csr *csr, const void *x, void *y, double alpha, double beta,
+                            void *stream);
+dtans_status dtans_csr_spmm(dtans_csr *csr, int32_t k, const void *X, int64_t ldx, void *Y,
+                            int64_t ldy, double alpha, double beta, void *stream);
+/* bytes one multiplication reads besides x and y (row_ptr, col_idx, vals, plan) */
+int64_t dtans_csr_bytes(const dtans_csr *csr);
+void dtans_csr_destroy(dtans_csr *csr);
+
+/*
+ * Autotuner: encodes the CSR matrix with candidate layouts, lane lengths and
+ * launch shapes, times each on the current device with k right-hand sides
+ * (k = 1: SpMV), and writes the fastest options to *inout (only the fields
+ * left at 0 / AUTO are searched).  budget_s bounds the wall time spent.
+ * *best_ms receives the best time per multiplication.  Needs a GPU.
+ */
+dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, const void *vals, dtans_dtype dtype, int32_t k,
+                            double budget_s, dtans_encode_opts *inout, double *best_ms);
+
+/* Release a handle and its device memory (NULL is ignored). */
+void dtans_destroy(dtans_matrix *mat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTANS_H */

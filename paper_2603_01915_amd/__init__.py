@@ -1,0 +1,347 @@
+"""dtANS-compressed sparse matrix-vector multiplication on AMD MI355X (gfx950).
+
+Python front end of libdtans: argument marshalling around the C ABI of
+``include/dtans.h``.  Encoding runs in the library's C++ host code and every
+multiplication in its HIP kernels; PyTorch only provides device memory and
+the current HIP stream.  Importing works without a GPU; calls that launch
+kernels need one, and everything fails loudly if ``libdtans.so`` is missing.
+
+    A = Matrix.from_csr(row_ptr, col, vals, n)   # encode once (host)
+    y = A.spmv(x)                                # y = A x, decoded on the fly
+    Y = A.spmm(X)                                # k right-hand sides
+    dX = A.spmm_t(dY)                            # A^T dY by decode-and-scatter
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import DtansError, EncodeOpts, Info, LAYOUT_AUTO, LAYOUT_NNZ, LAYOUT_ROW
+
+__all__ = ["Matrix", "CsrBaseline", "Batch", "DtansError", "autotune", "version",
+           "LAYOUT_AUTO", "LAYOUT_ROW", "LAYOUT_NNZ"]
+
+_LAYOUTS = {"auto": LAYOUT_AUTO, "row": LAYOUT_ROW, "nnz": LAYOUT_NNZ,
+            LAYOUT_AUTO: LAYOUT_AUTO, LAYOUT_ROW: LAYOUT_ROW, LAYOUT_NNZ: LAYOUT_NNZ}
+
+
+def version() -> str:
+    return _lib.load().dtans_version().decode()
+
+
+def _np(a, dtype=None) -> np.ndarray:
+    if hasattr(a, "detach"):  # torch tensor on the host
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dtype_code(vals: np.ndarray) -> int:
+    if vals.dtype == np.float64:
+        return _lib.F64
+    if vals.dtype == np.float32:
+        return _lib.F32
+    raise TypeError("values must be float32 or float64, got %s" % vals.dtype)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _dev(t, dtype, name: str, dims: int):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.dim() != dims:
+        raise ValueError("%s must have %d dimension(s)" % (name, dims))
+    if dims == 1 and t.stride(0) != 1:
+        raise ValueError("%s must be contiguous" % name)
+    if dims == 2 and t.size(1) > 0 and t.stride(1) != 1:
+        raise ValueError("%s must be row-major with unit column stride" % name)
+    return t
+
+
+def _ld(t) -> int:
+    return max(int(t.stride(0)), int(t.size(1)), 1)
+
+
+class Matrix:
+    """A CSR matrix encoded in CSR-dtANS (host container + device copy)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        self._L = _lib.load()
+        inf = self.info()
+        self.shape = (inf["m"], inf["n"])
+        self.nnz = inf["nnz"]
+        self.is_f64 = inf["dtype"] == _lib.F64
+
+    # --------------------------------------------------------- construction
+    @classmethod
+    def from_csr(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
+                 waves_per_wg: int = 0, wg_per_cu: int = 0, sort_rows: bool = False,
+                 seed: int = 1) -> "Matrix":
+        L = _lib.load()
+        rp = _np(row_ptr, np.int32)
+        ci = _np(col, np.int32)
+        v = _np(vals)
+        if v.dtype not in (np.float32, np.float64):
+            v = v.astype(np.float64)
+        m, nnz = len(rp) - 1, len(ci)
+        o = EncodeOpts()
+        L.dtans_default_opts(ctypes.byref(o))
+        o.layout = _LAYOUTS[layout]
+        o.lane_nnz = lane_nnz
+        o.waves_per_wg = waves_per_wg
+        o.wg_per_cu = wg_per_cu
+        o.sort_rows = int(bool(sort_rows))
+        o.perm_seed = seed
+        h = ctypes.c_void_p()
+        _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
+                                      ctypes.byref(o), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str) -> "Matrix":
+        L = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(L.dtans_load(str(path).encode(), ctypes.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str) -> None:
+        _lib.check(self._L.dtans_save(self._h, str(path).encode()))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.dtans_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- queries
+    def info(self) -> dict:
+        inf = Info()
+        _lib.check(self._L.dtans_matrix_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.is_f64 else torch.float32
+
+    def set_launch(self, waves_per_wg: int = 0, wg_per_cu: int = 0) -> None:
+        _lib.check(self._L.dtans_set_launch(self._h, waves_per_wg, wg_per_cu))
+
+    def to_device(self, stream=None) -> "Matrix":
+        _lib.check(self._L.dtans_to_device(self._h, ctypes.c_void_p(_stream(stream))))
+        return self
+
+    # ---------------------------------------------------------- multiplies
+    def spmv(self, x, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """y = alpha * A x + beta * y (device tensors)."""
+        torch = _torch()
+        m, n = self.shape
+        _dev(x, self.torch_dtype, "x", 1)
+        if x.numel() != n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), n))
+        if y is None:
+            y = torch.empty(m, dtype=self.torch_dtype, device=x.device)
+            beta = 0.0
+        _dev(y, self.torch_dtype, "y", 1)
+        if y.numel() != m:
+            raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
+        _lib.check(self._L.dtans_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
+                                      ctypes.c_void_p(_stream(stream))))
+        return y
+
+    def spmm(self, X, Y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """Y = alpha * A X + beta * Y with X [n, k] and Y [m, k] row-major."""
+        torch = _torch()
+        m, n = self.shape
+        _dev(X, self.torch_dtype, "X", 2)
+        if X.size(0) != n:
+            raise ValueError("X has %d rows, expected %d" % (X.size(0), n))
+        k = X.size(1)
+        if Y is None:
+            Y = torch.empty((m, k), dtype=self.torch_dtype, device=X.device)
+            beta = 0.0
+        _dev(Y, self.torch_dtype, "Y", 2)
+        if tuple(Y.shape) != (m, k):
+            raise ValueError("Y must be [%d, %d]" % (m, k))
+        if k == 0:
+            return Y
+        _lib.check(self._L.dtans_spmm(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
+                                      alpha, beta, ctypes.c_void_p(_stream(stream))))
+        return Y
+
+    def spmm_t(self, dY, dX=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """dX = alpha * A^T dY + beta * dX with dY [m, k] and dX [n, k]."""
+        torch = _torch()
+        m, n = self.shape
+        _dev(dY, self.torch_dtype, "dY", 2)
+        if dY.size(0) != m:
+            raise ValueError("dY has %d rows, expected %d" % (dY.size(0), m))
+        k = dY.size(1)
+        if dX is None:
+            dX = torch.empty((n, k), dtype=self.torch_dtype, device=dY.device)
+            beta = 0.0
+        _dev(dX, self.torch_dtype, "dX", 2)
+        if tuple(dX.shape) != (n, k):
+            raise ValueError("dX must be [%d, %d]" % (n, k))
+        if k == 0:
+            return dX
+        _lib.check(self._L.dtans_spmm_t(self._h, k, dY.data_ptr(), _ld(dY), dX.data_ptr(),
+                                        _ld(dX), alpha, beta, ctypes.c_void_p(_stream(stream))))
+        return dX
+
+    def decode_csr(self, device=None, stream=None):
+        """Decode to CSR on the GPU: (row_ptr int32, col int32, vals) tensors."""
+        torch = _torch()
+        m, _ = self.shape
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        rp = torch.empty(m + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        v = torch.empty(max(self.nnz, 1), dtype=self.torch_dtype, device=dev)
+        _lib.check(self._L.dtans_decode_csr(self._h, rp.data_ptr(), ci.data_ptr(), v.data_ptr(),
+                                            ctypes.c_void_p(_stream(stream))))
+        return rp, ci[:self.nnz], v[:self.nnz]
+
+
+class CsrBaseline:
+    """Plain (uncompressed) CSR SpMV/SpMM on the same GPU, for comparison."""
+
+    def __init__(self, row_ptr, col, vals, n: int, variant: int = 0):
+        self._L = _lib.load()
+        rp = _np(row_ptr, np.int32)
+        ci = _np(col, np.int32)
+        v = _np(vals)
+        self.shape = (len(rp) - 1, n)
+        self.nnz = len(ci)
+        self.is_f64 = v.dtype == np.float64
+        h = ctypes.c_void_p()
+        _lib.check(self._L.dtans_csr_create(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
+                                            _dtype_code(v), variant, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def bytes(self) -> int:
+        return int(self._L.dtans_csr_bytes(self._h))
+
+    def spmv(self, x, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        torch = _torch()
+        dt = torch.float64 if self.is_f64 else torch.float32
+        _dev(x, dt, "x", 1)
+        if y is None:
+            y = torch.empty(self.shape[0], dtype=dt, device=x.device)
+            beta = 0.0
+        _dev(y, dt, "y", 1)
+        _lib.check(self._L.dtans_csr_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
+                                          ctypes.c_void_p(_stream(stream))))
+        return y
+
+    def spmm(self, X, Y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        torch = _torch()
+        dt = torch.float64 if self.is_f64 else torch.float32
+        _dev(X, dt, "X", 2)
+        k = X.size(1)
+        if Y is None:
+            Y = torch.empty((self.shape[0], k), dtype=dt, device=X.device)
+            beta = 0.0
+        _dev(Y, dt, "Y", 2)
+        _lib.check(self._L.dtans_csr_spmm(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
+                                          alpha, beta, ctypes.c_void_p(_stream(stream))))
+        return Y
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.dtans_csr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several encoded matrices multiplied in one persistent launch."""
+
+    def __init__(self, matrices: Sequence[Matrix]):
+        self._L = _lib.load()
+        self.matrices = list(matrices)
+        arr = (ctypes.c_void_p * len(self.matrices))(*[m._h.value for m in self.matrices])
+        h = ctypes.c_void_p()
+        _lib.check(self._L.dtans_batch_create(len(self.matrices), arr, ctypes.byref(h)))
+        self._h = h
+
+    def spmv(self, xs, ys=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        torch = _torch()
+        if ys is None:
+            ys = [torch.empty(m.shape[0], dtype=m.torch_dtype, device=x.device)
+                  for m, x in zip(self.matrices, xs)]
+            beta = 0.0
+        for m, x, y in zip(self.matrices, xs, ys):
+            _dev(x, m.torch_dtype, "x", 1)
+            _dev(y, m.torch_dtype, "y", 1)
+            if x.numel() != m.shape[1] or y.numel() != m.shape[0]:
+                raise ValueError("vector sizes do not match the matrices")
+        cnt = len(self.matrices)
+        xa = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+        ya = (ctypes.c_void_p * cnt)(*[y.data_ptr() for y in ys])
+        _lib.check(self._L.dtans_batch_spmv(self._h, xa, ya, alpha, beta,
+                                            ctypes.c_void_p(_stream(stream))))
+        return ys
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.dtans_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(row_ptr, col, vals, n: int, k: int = 1, budget_s: float = 20.0,
+             layout="auto", lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0):
+    """Search layout, nonzeros per lane and launch shape on the current GPU.
+    Returns (options dict, best milliseconds per multiplication)."""
+    L = _lib.load()
+    rp = _np(row_ptr, np.int32)
+    ci = _np(col, np.int32)
+    v = _np(vals)
+    o = EncodeOpts()
+    L.dtans_default_opts(ctypes.byref(o))
+    o.layout = _LAYOUTS[layout]
+    o.lane_nnz = lane_nnz
+    o.waves_per_wg = waves_per_wg
+    o.wg_per_cu = wg_per_cu
+    best = ctypes.c_double()
+    _lib.check(L.dtans_autotune(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
+                                _dtype_code(v), k, budget_s, ctypes.byref(o), ctypes.byref(best)))
+    opts = {"layout": o.layout, "lane_nnz": o.lane_nnz, "waves_per_wg": o.waves_per_wg,
+            "wg_per_cu": o.wg_per_cu}
+    return opts, best.value

@@ -1,0 +1,663 @@
+// C ABI of libdtans (declared in include/dtans.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "container.hpp"
+#include "dtans.h"
+#include "kernels.hpp"
+
+using namespace dtans;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dtans_status set_err(dtans_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+dtans_status from_msg(const std::string &m) {
+    if (m.empty()) return DTANS_OK;
+    struct { const char *p; dtans_status s; } map[] = {
+        {"EINVAL", DTANS_EINVAL}, {"EUNSORTED", DTANS_EUNSORTED}, {"ERANGE", DTANS_ERANGE},
+        {"ENOMEM", DTANS_ENOMEM}, {"ECORRUPT", DTANS_ECORRUPT}, {"EIO", DTANS_EIO},
+        {"EUNSUPPORTED", DTANS_EUNSUPPORTED}};
+    for (auto &e : map)
+        if (m.compare(0, strlen(e.p), e.p) == 0 && m.size() > strlen(e.p) && m[strlen(e.p)] == ':')
+            return set_err(e.s, m);
+    return set_err(DTANS_EINVAL, m);
+}
+
+dtans_status hip_err(hipError_t e, const char *what) {
+    return set_err(DTANS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                            \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_err(e_, #call);         \
+    } while (0)
+
+int device_cus(int dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+// Device memory owned by a handle; freed in one place.
+struct DevBufs {
+    std::vector<void *> ptrs;
+    ~DevBufs() { release(); }
+    void release() {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+    // copy `bytes` from host (or zero-fill when src is null) into a new buffer
+    // padded by `pad` zero bytes
+    hipError_t upload(void **dst, const void *src, size_t bytes, hipStream_t st, size_t pad = 256) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes + pad);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(p);
+        e = hipMemsetAsync(p, 0, bytes + pad, st);
+        if (e != hipSuccess) return e;
+        if (src && bytes) e = hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st);
+        *dst = p;
+        return e;
+    }
+};
+
+}  // namespace
+
+struct dtans_matrix {
+    Container c;
+    std::vector<uint64_t> gtab;
+    std::vector<uint8_t> gval;
+    std::vector<int32_t> lane_row, split_row, split_first, split_last;
+    DevBufs bufs;
+    bool uploaded = false;
+    int device = -1, num_cus = 256;
+    int waves_per_wg = 0, wg_per_cu = 0;
+    DevMat view{};
+    double *partial = nullptr;
+    size_t partial_cap = 0;  // doubles
+};
+
+struct dtans_batch {
+    std::vector<dtans_matrix *> mats;
+    bool f64 = true;
+    DevBufs bufs;
+    BatchDev dev{};
+    Launch launch{};
+    std::vector<BatchTask> tasks;
+    std::vector<int32_t> wg_task;
+};
+
+struct dtans_csr {
+    int64_t m = 0, n = 0, nnz = 0;
+    bool f64 = true;
+    DevBufs bufs;
+    CsrDev dev{};
+    int device = -1, num_cus = 256;
+    double *partial = nullptr;
+    size_t partial_cap = 0;
+    int64_t bytes = 0;
+};
+
+namespace {
+
+Launch plan_launch(const dtans_matrix *h) {
+    const bool f64 = h->c.dtype == kF64;
+    const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
+    const int lds_per_cu = 160 * 1024;
+    // LDS admits lds_per_cu / table_bytes workgroups per CU (2 for FP64, 3 for
+    // FP32); the decode kernels are register-limited to 7 waves per SIMD, so
+    // 14 (FP64) or 9 (FP32) waves per workgroup fill 28 / 27 of 28 slots
+    int wgcu = h->wg_per_cu > 0 ? h->wg_per_cu : std::max(1, lds_per_cu / table_bytes);
+    int wpw = h->waves_per_wg > 0 ? h->waves_per_wg : (f64 ? 14 : 9);
+    Launch L;
+    L.waves_per_wg = wpw;
+    int64_t need = (h->c.num_waves + wpw - 1) / wpw;
+    int64_t grid = (int64_t)h->num_cus * wgcu;
+    L.grid = (int)std::max<int64_t>(1, std::min(grid, need));
+    return L;
+}
+
+dtans_status upload(dtans_matrix *h, hipStream_t st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (h->uploaded) {
+        if (dev != h->device)
+            return set_err(DTANS_EINVAL, "matrix was uploaded to device " + std::to_string(h->device) +
+                                             ", current device is " + std::to_string(dev));
+        return DTANS_OK;
+    }
+    const Container &c = h->c;
+    gpu_table(c, h->gtab, h->gval);
+    nnz_layout_meta(c, h->lane_row, h->split_row, h->split_first, h->split_last);
+    const bool f64 = c.dtype == kF64;
+    const void *escv_src = c.escv.data();
+    size_t escv_bytes = c.escv.size() * 8;
+    std::vector<uint32_t> escv32;
+    if (!f64) {
+        escv32.resize(c.escv.size());
+        for (size_t i = 0; i < c.escv.size(); ++i) escv32[i] = (uint32_t)c.escv[i];
+        escv_src = escv32.data();
+        escv_bytes = escv32.size() * 4;
+    }
+    void *p[13];
+    HIP_TRY(h->bufs.upload(&p[0], h->gtab.data(), 8 * h->gtab.size(), st));
+    HIP_TRY(h->bufs.upload(&p[1], h->gval.data(), h->gval.size(), st));
+    HIP_TRY(h->bufs.upload(&p[2], c.row_ptr.data(), 4 * c.row_ptr.size(), st));
+    HIP_TRY(h->bufs.upload(&p[3], c.word_off.data(), 8 * c.word_off.size(), st));
+    HIP_TRY(h->bufs.upload(&p[4], c.escd_off.data(), 8 * c.escd_off.size(), st));
+    HIP_TRY(h->bufs.upload(&p[5], c.escv_off.data(), 8 * c.escv_off.size(), st));
+    HIP_TRY(h->bufs.upload(&p[6], c.words.data(), 4 * c.words.size(), st));
+    HIP_TRY(h->bufs.upload(&p[7], c.escd.data(), 4 * c.escd.size(), st));
+    HIP_TRY(h->bufs.upload(&p[8], escv_src, escv_bytes, st));
+    HIP_TRY(h->bufs.upload(&p[9], h->lane_row.data(), 4 * h->lane_row.size(), st));
+    HIP_TRY(h->bufs.upload(&p[10], h->split_row.data(), 4 * h->split_row.size(), st));
+    HIP_TRY(h->bufs.upload(&p[11], h->split_first.data(), 4 * h->split_first.size(), st));
+    HIP_TRY(h->bufs.upload(&p[12], h->split_last.data(), 4 * h->split_last.size(), st));
+    // the host staging vectors above must outlive the copies
+    HIP_TRY(hipStreamSynchronize(st));
+    DevMat &v = h->view;
+    v.tab = (const uint64_t *)p[0];
+    v.tabval = p[1];
+    v.row_ptr = (const int32_t *)p[2];
+    v.woff = (const uint64_t *)p[3];
+    v.doff = (const uint64_t *)p[4];
+    v.voff = (const uint64_t *)p[5];
+    v.words = (const uint32_t *)p[6];
+    v.escd = (const uint32_t *)p[7];
+    v.escv = p[8];
+    v.lane_row = (const int32_t *)p[9];
+    v.split_row = (const int32_t *)p[10];
+    v.split_first = (const int32_t *)p[11];
+    v.split_last = (const int32_t *)p[12];
+    v.m = c.m;
+    v.n = c.n;
+    v.nnz = c.nnz;
+    v.num_lanes = c.num_lanes;
+    v.num_waves = c.num_waves;
+    v.nsplit = (int64_t)h->split_row.size();
+    v.lane_nnz = (int32_t)c.lane_nnz;
+    v.layout = (int32_t)c.layout;
+    h->device = dev;
+    h->num_cus = device_cus(dev);
+    h->uploaded = true;
+    return DTANS_OK;
+}
+
+dtans_status ensure_partial(double *&buf, size_t &cap, size_t need) {
+    if (need <= cap) return DTANS_OK;
+    if (buf) {
+        hipError_t e = hipDeviceSynchronize();  // earlier launches may still use it
+        if (e != hipSuccess) return hip_err(e, "hipDeviceSynchronize");
+        (void)hipFree(buf);
+        buf = nullptr;
+        cap = 0;
+    }
+    HIP_TRY(hipMalloc((void **)&buf, need * sizeof(double)));
+    cap = need;
+    return DTANS_OK;
+}
+
+dtans_status check_handle(dtans_matrix *h, hipStream_t st) {
+    if (!h) return set_err(DTANS_EINVAL, "null matrix handle");
+    return upload(h, st);
+}
+
+int64_t sell_bytes(const Container &c, int slice) {
+    int64_t total = 4 * ((c.m + slice - 1) / slice + 1);
+    const int64_t per = 4 + (int64_t)c.value_bytes();
+    for (int64_t s = 0; s < c.m; s += slice) {
+        int64_t mx = 0;
+        for (int64_t i = s; i < std::min(c.m, s + slice); ++i)
+            mx = std::max<int64_t>(mx, c.row_ptr[i + 1] - c.row_ptr[i]);
+        total += slice * mx * per;
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dtans_version(void) { return "dtans 0.1.0 (gfx950, CSR-dtANS container v1)"; }
+
+const char *dtans_last_error(void) { return g_last_error.c_str(); }
+
+void dtans_default_opts(dtans_encode_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->layout = DTANS_LAYOUT_AUTO;
+    o->perm_seed = 1;
+}
+
+dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                              const dtans_encode_opts *opts, dtans_matrix **out) {
+    if (!out) return set_err(DTANS_EINVAL, "out is null");
+    *out = nullptr;
+    dtans_encode_opts o;
+    dtans_default_opts(&o);
+    if (opts) o = *opts;
+    if (m < 0 || n < 0 || nnz < 0) return set_err(DTANS_EINVAL, "negative size");
+    if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31))
+        return set_err(DTANS_ERANGE, "rows, columns and nonzeros must be below 2^31");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null array");
+    if (o.waves_per_wg < 0 || o.waves_per_wg > 16 || o.wg_per_cu < 0 || o.wg_per_cu > 32)
+        return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
+    const size_t vb = dtype == DTANS_F64 ? 8 : 4;
+    std::vector<int32_t> scol;
+    std::vector<uint8_t> sval;
+    if (o.sort_rows && nnz > 0) {
+        if (row_ptr[0] != 0 || row_ptr[m] != nnz) return set_err(DTANS_EINVAL, "row_ptr must run from 0 to nnz");
+        scol.assign(col_idx, col_idx + nnz);
+        sval.assign((const uint8_t *)vals, (const uint8_t *)vals + nnz * vb);
+        std::vector<int64_t> idx;
+        for (int64_t i = 0; i < m; ++i) {
+            if (row_ptr[i + 1] < row_ptr[i]) return set_err(DTANS_EINVAL, "row_ptr decreases");
+            int64_t b = row_ptr[i], e = row_ptr[i + 1];
+            idx.resize(e - b);
+            for (int64_t q = b; q < e; ++q) idx[q - b] = q;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int64_t a, int64_t c) { return col_idx[a] < col_idx[c]; });
+            for (int64_t q = b; q < e; ++q) {
+                scol[q] = col_idx[idx[q - b]];
+                memcpy(&sval[q * vb], (const uint8_t *)vals + idx[q - b] * vb, vb);
+            }
+        }
+        col_idx = scol.data();
+        vals = sval.data();
+    }
+    EncodeParams p;
+    p.seed = o.perm_seed;
+    int layout = o.layout;
+    if (layout == DTANS_LAYOUT_AUTO) {
+        // one row per lane unless the rows are long or irregular enough that
+        // 64-row waves would be too few or badly balanced
+        int64_t maxlen = 0;
+        for (int64_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
+        double mean = m ? (double)nnz / m : 0;
+        int64_t waves = (m + 63) / 64;
+        layout = (waves < 2048 || maxlen > 8 * std::max(mean, 4.0)) ? DTANS_LAYOUT_NNZ : DTANS_LAYOUT_ROW;
+    }
+    p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
+    if (p.layout == kLayoutNnz) {
+        int T = o.lane_nnz;
+        if (T == 0) {
+            // enough lanes for ~8 waves per SIMD of the device, 32..512 nonzeros each
+            int64_t lanes_target = 256LL * 4 * 8 * 64;
+            int64_t t = nnz / std::max<int64_t>(1, lanes_target);
+            T = (int)std::min<int64_t>(512, std::max<int64_t>(32, (t + 3) / 4 * 4));
+        }
+        p.lane_nnz = (uint32_t)T;
+    }
+    dtans_matrix *h = new dtans_matrix();
+    std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c);
+    if (!err.empty()) {
+        delete h;
+        return from_msg(err);
+    }
+    h->waves_per_wg = o.waves_per_wg;
+    h->wg_per_cu = o.wg_per_cu;
+    *out = h;
+    return DTANS_OK;
+}
+
+dtans_status dtans_save(const dtans_matrix *mat, const char *path) {
+    if (!mat || !path) return set_err(DTANS_EINVAL, "null argument");
+    return from_msg(save_container(mat->c, path));
+}
+
+dtans_status dtans_load(const char *path, dtans_matrix **out) {
+    if (!path || !out) return set_err(DTANS_EINVAL, "null argument");
+    *out = nullptr;
+    dtans_matrix *h = new dtans_matrix();
+    std::string err = load_container(path, h->c);
+    if (err.empty()) err = host_decode(h->c, nullptr, nullptr);
+    if (!err.empty()) {
+        delete h;
+        return from_msg(err);
+    }
+    *out = h;
+    return DTANS_OK;
+}
+
+dtans_status dtans_to_device(dtans_matrix *mat, void *stream) {
+    return check_handle(mat, (hipStream_t)stream);
+}
+
+dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu) {
+    if (!mat) return set_err(DTANS_EINVAL, "null matrix handle");
+    if (waves_per_wg < 0 || waves_per_wg > 16 || wg_per_cu < 0 || wg_per_cu > 32)
+        return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
+    if (waves_per_wg) mat->waves_per_wg = waves_per_wg;
+    if (wg_per_cu) mat->wg_per_cu = wg_per_cu;
+    return DTANS_OK;
+}
+
+dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
+    if (!mat || !o) return set_err(DTANS_EINVAL, "null argument");
+    const Container &c = mat->c;
+    memset(o, 0, sizeof(*o));
+    const int64_t vb = (int64_t)c.value_bytes();
+    o->m = c.m;
+    o->n = c.n;
+    o->nnz = c.nnz;
+    o->dtype = (int32_t)c.dtype;
+    o->layout = (int32_t)c.layout;
+    o->lane_nnz = (int32_t)c.lane_nnz;
+    o->waves_per_wg = plan_launch(mat).waves_per_wg;
+    o->num_lanes = c.num_lanes;
+    o->num_waves = c.num_waves;
+    o->words = (int64_t)c.words.size();
+    o->esc_delta = (int64_t)c.escd.size();
+    o->esc_value = (int64_t)c.escv.size();
+    o->table_bytes = (int64_t)kSlots * (8 + vb);
+    o->stream_bytes = 4 * o->words + 4 * o->esc_delta + vb * o->esc_value;
+    int64_t nsplit = 0;
+    if (c.layout == kLayoutNnz) {
+        std::vector<int32_t> lr, sr, sf, sl;
+        nnz_layout_meta(c, lr, sr, sf, sl);
+        nsplit = (int64_t)sr.size();
+    }
+    o->index_bytes = 4 * (c.m + 1) + 3 * 8 * (c.num_waves + 1) +
+                     (c.layout == kLayoutNnz ? 4 * c.num_lanes + 12 * nsplit : 0);
+    o->total_bytes = o->table_bytes + o->stream_bytes + o->index_bytes;
+    o->csr_bytes = 4 * (c.m + 1) + c.nnz * (4 + vb);
+    o->coo_bytes = c.nnz * (8 + vb);
+    o->sell_bytes = sell_bytes(c, 32);
+    o->delta_symbols = c.dtab.symbols;
+    o->value_symbols = c.vtab.symbols;
+    o->delta_entropy = c.dtab.entropy;
+    o->value_entropy = c.vtab.entropy;
+    o->delta_cross_entropy = c.dtab.cross_entropy;
+    o->value_cross_entropy = c.vtab.cross_entropy;
+    o->bits_per_nnz = c.nnz ? 8.0 * o->stream_bytes / c.nnz : 0.0;
+    return DTANS_OK;
+}
+
+dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
+                        int64_t ldy, double alpha, double beta, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    dtans_status s = check_handle(mat, st);
+    if (s) return s;
+    const Container &c = mat->c;
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    if (ldx < k || ldy < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
+    if ((c.m > 0 && !Y) || (c.n > 0 && c.nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
+    if (c.layout == kLayoutNnz) {
+        s = ensure_partial(mat->partial, mat->partial_cap, (size_t)(2 * c.num_lanes * std::min(k, 32)) + 1);
+        if (s) return s;
+    }
+    hipError_t e = launch_spmm(mat->view, c.dtype == kF64, k, X, ldx, Y, ldy, alpha, beta,
+                               mat->partial, plan_launch(mat), st);
+    if (e != hipSuccess) return hip_err(e, "dtans_spmm launch");
+    return DTANS_OK;
+}
+
+dtans_status dtans_spmv(dtans_matrix *mat, const void *x, void *y, double alpha, double beta,
+                        void *stream) {
+    return dtans_spmm(mat, 1, x, 1, y, 1, alpha, beta, stream);
+}
+
+dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t lddy, void *dX,
+                          int64_t lddx, double alpha, double beta, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    dtans_status s = check_handle(mat, st);
+    if (s) return s;
+    const Container &c = mat->c;
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    if (lddy < k || lddx < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
+    if ((c.n > 0 && !dX) || (c.m > 0 && c.nnz > 0 && !dY)) return set_err(DTANS_EINVAL, "null vector");
+    hipError_t e = launch_spmm_t(mat->view, c.dtype == kF64, k, dY, lddy, dX, lddx, alpha, beta,
+                                 plan_launch(mat), st);
+    if (e != hipSuccess) return hip_err(e, "dtans_spmm_t launch");
+    return DTANS_OK;
+}
+
+dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_idx, void *vals,
+                              void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    dtans_status s = check_handle(mat, st);
+    if (s) return s;
+    const Container &c = mat->c;
+    if (!row_ptr || (c.nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null output");
+    HIP_TRY(hipMemcpyAsync(row_ptr, mat->view.row_ptr, 4 * (size_t)(c.m + 1),
+                           hipMemcpyDeviceToDevice, st));
+    hipError_t e = launch_decode(mat->view, c.dtype == kF64, col_idx, vals, plan_launch(mat), st);
+    if (e != hipSuccess) return hip_err(e, "dtans_decode_csr launch");
+    return DTANS_OK;
+}
+
+void dtans_destroy(dtans_matrix *mat) {
+    if (!mat) return;
+    if (mat->partial) (void)hipFree(mat->partial);
+    delete mat;
+}
+
+// ------------------------------------------------------------------ batch
+dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_batch **out) {
+    if (!out || !mats || count <= 0) return set_err(DTANS_EINVAL, "need at least one matrix");
+    *out = nullptr;
+    if (count > kMaxBatch) return set_err(DTANS_EINVAL, "at most 128 matrices per batch");
+    const bool f64 = mats[0] && mats[0]->c.dtype == kF64;
+    for (int i = 0; i < count; ++i) {
+        if (!mats[i]) return set_err(DTANS_EINVAL, "null matrix in batch");
+        if ((mats[i]->c.dtype == kF64) != f64) return set_err(DTANS_EINVAL, "batch matrices must share a dtype");
+        if (mats[i]->c.layout != kLayoutRow)
+            return set_err(DTANS_EUNSUPPORTED, "batch matrices must use the ROW layout");
+        dtans_status s = upload(mats[i], nullptr);
+        if (s) return s;
+        if (mats[i]->device != mats[0]->device) return set_err(DTANS_EINVAL, "batch matrices on different devices");
+    }
+    dtans_batch *b = new dtans_batch();
+    b->mats.assign(mats, mats + count);
+    b->f64 = f64;
+    // cost of each encoded wave: its stream words plus a fixed per-wave cost
+    std::vector<int32_t> wmat;
+    std::vector<int32_t> wid;
+    std::vector<double> cost;
+    for (int i = 0; i < count; ++i) {
+        const Container &c = mats[i]->c;
+        for (int64_t w = 0; w < c.num_waves; ++w) {
+            wmat.push_back(i);
+            wid.push_back((int32_t)w);
+            cost.push_back((double)(c.word_off[w + 1] - c.word_off[w]) + 256.0);
+        }
+    }
+    const bool f64tab = f64;
+    const int table_bytes = kSlots * (8 + (f64tab ? 8 : 4));
+    const int wgcu = std::max(1, 160 * 1024 / table_bytes);
+    const int wpw = f64tab ? 14 : 9;
+    const int64_t total_waves = (int64_t)wmat.size();
+    int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)mats[0]->num_cus * wgcu,
+                                                           (total_waves + wpw - 1) / wpw));
+    // contiguous ranges of about equal cost, one per workgroup, each split
+    // into per-matrix tasks
+    std::vector<double> prefix(total_waves + 1, 0.0);
+    for (int64_t i = 0; i < total_waves; ++i) prefix[i + 1] = prefix[i] + cost[i];
+    b->wg_task.push_back(0);
+    int64_t w = 0;
+    for (int g = 0; g < grid; ++g) {
+        const double goal = prefix[total_waves] * (g + 1) / grid;
+        int64_t end = g == grid - 1 ? total_waves
+                                    : std::lower_bound(prefix.begin(), prefix.end(), goal) - prefix.begin();
+        end = std::max(w, std::min(end, total_waves));
+        for (int64_t q = w; q < end;) {
+            int64_t e = q;
+            while (e < end && wmat[e] == wmat[q]) ++e;
+            b->tasks.push_back({wmat[q], wid[q], (int32_t)(e - q), 0});
+            q = e;
+        }
+        b->wg_task.push_back((int32_t)b->tasks.size());
+        w = end;
+    }
+    std::vector<DevMat> views(count);
+    for (int i = 0; i < count; ++i) views[i] = mats[i]->view;
+    void *p_mats, *p_tasks, *p_wg;
+    hipStream_t st = nullptr;
+    hipError_t e;
+    if ((e = b->bufs.upload(&p_mats, views.data(), sizeof(DevMat) * views.size(), st)) != hipSuccess ||
+        (e = b->bufs.upload(&p_tasks, b->tasks.data(), sizeof(BatchTask) * b->tasks.size(), st)) != hipSuccess ||
+        (e = b->bufs.upload(&p_wg, b->wg_task.data(), 4 * b->wg_task.size(), st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        delete b;
+        return hip_err(e, "dtans_batch_create upload");
+    }
+    b->dev.mats = (const DevMat *)p_mats;
+    b->dev.tasks = (const BatchTask *)p_tasks;
+    b->dev.wg_task = (const int32_t *)p_wg;
+    b->launch.waves_per_wg = wpw;
+    b->launch.grid = grid;
+    *out = b;
+    return DTANS_OK;
+}
+
+dtans_status dtans_batch_spmv(dtans_batch *b, const void *const *xs, void *const *ys, double alpha,
+                              double beta, void *stream) {
+    if (!b || !xs || !ys) return set_err(DTANS_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cnt = b->mats.size();
+    BatchDev dev = b->dev;
+    for (size_t i = 0; i < cnt; ++i) {
+        if ((b->mats[i]->c.m > 0 && !ys[i]) || (b->mats[i]->c.nnz > 0 && !xs[i]))
+            return set_err(DTANS_EINVAL, "null vector in batch");
+        dev.xs[i] = xs[i];
+        dev.ys[i] = ys[i];
+    }
+    hipError_t e = launch_batch(dev, b->f64, alpha, beta, b->launch, st);
+    if (e != hipSuccess) return hip_err(e, "dtans_batch_spmv launch");
+    return DTANS_OK;
+}
+
+void dtans_batch_destroy(dtans_batch *b) { delete b; }
+
+// -------------------------------------------------------------- CSR baseline
+dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                              int32_t variant, dtans_csr **out) {
+    if (!out) return set_err(DTANS_EINVAL, "out is null");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && (!col_idx || !vals)))
+        return set_err(DTANS_EINVAL, "bad CSR arguments");
+    if (dtype != DTANS_F32 && dtype != DTANS_F64) return set_err(DTANS_EINVAL, "bad dtype");
+    if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31)) return set_err(DTANS_ERANGE, "sizes must be below 2^31");
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return set_err(DTANS_EINVAL, "row_ptr must run from 0 to nnz");
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return set_err(DTANS_EINVAL, "row_ptr decreases");
+        maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
+    }
+    for (int64_t q = 0; q < nnz; ++q)
+        if (col_idx[q] < 0 || col_idx[q] >= n) return set_err(DTANS_ERANGE, "column index out of range");
+    const double mean = m ? (double)nnz / m : 0.0;
+    if (variant == 0) variant = (maxlen > 16 * std::max(mean, 4.0)) ? 2 : 1;
+    if (variant != 1 && variant != 2) return set_err(DTANS_EINVAL, "variant must be 0, 1 or 2");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    dtans_csr *h = new dtans_csr();
+    h->m = m;
+    h->n = n;
+    h->nnz = nnz;
+    h->f64 = dtype == DTANS_F64;
+    h->device = dev;
+    h->num_cus = device_cus(dev);
+    const size_t vb = h->f64 ? 8 : 4;
+    CsrDev &c = h->dev;
+    c.m = m;
+    c.n = n;
+    c.nnz = nnz;
+    c.variant = variant;
+    int G = 1;
+    while (G < 64 && G < mean) G <<= 1;
+    c.group = G;
+    c.lane_nnz = 32;
+    std::vector<int32_t> lane_row, split_row, split_first, split_last;
+    if (variant == 2) {
+        Container tmp;  // only row_ptr and the lane geometry are used
+        tmp.layout = kLayoutNnz;
+        tmp.lane_nnz = (uint32_t)c.lane_nnz;
+        tmp.m = m;
+        tmp.nnz = nnz;
+        tmp.num_lanes = (nnz + c.lane_nnz - 1) / c.lane_nnz;
+        tmp.row_ptr.assign(row_ptr, row_ptr + m + 1);
+        nnz_layout_meta(tmp, lane_row, split_row, split_first, split_last);
+        c.num_lanes = tmp.num_lanes;
+        c.nsplit = (int64_t)split_row.size();
+    }
+    void *p[7];
+    hipStream_t st = nullptr;
+    hipError_t e;
+    if ((e = h->bufs.upload(&p[0], row_ptr, 4 * (size_t)(m + 1), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[1], col_idx, 4 * (size_t)nnz, st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[2], vals, vb * (size_t)nnz, st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[3], lane_row.data(), 4 * lane_row.size(), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[4], split_row.data(), 4 * split_row.size(), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[5], split_first.data(), 4 * split_first.size(), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[6], split_last.data(), 4 * split_last.size(), st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        delete h;
+        return hip_err(e, "dtans_csr_create upload");
+    }
+    c.row_ptr = (const int32_t *)p[0];
+    c.col = (const int32_t *)p[1];
+    c.val = p[2];
+    c.lane_row = (const int32_t *)p[3];
+    c.split_row = (const int32_t *)p[4];
+    c.split_first = (const int32_t *)p[5];
+    c.split_last = (const int32_t *)p[6];
+    h->bytes = 4 * (m + 1) + nnz * (4 + (int64_t)vb) +
+               (variant == 2 ? 4 * c.num_lanes + 12 * c.nsplit : 0);
+    *out = h;
+    return DTANS_OK;
+}
+
+dtans_status dtans_csr_spmm(dtans_csr *h, int32_t k, const void *X, int64_t ldx, void *Y,
+                            int64_t ldy, double alpha, double beta, void *stream) {
+    if (!h) return set_err(DTANS_EINVAL, "null CSR handle");
+    if (k < 1 || ldx < k || ldy < k) return set_err(DTANS_EINVAL, "bad k or leading dimension");
+    if ((h->m > 0 && !Y) || (h->nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) return set_err(DTANS_EINVAL, "CSR handle lives on another device");
+    if (h->dev.variant == 2) {
+        dtans_status s = ensure_partial(h->partial, h->partial_cap, (size_t)(2 * h->dev.num_lanes * std::min(k, 32)) + 1);
+        if (s) return s;
+    }
+    hipError_t e = launch_csr(h->dev, h->f64, k, X, ldx, Y, ldy, alpha, beta, h->partial, h->num_cus,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_err(e, "dtans_csr_spmm launch");
+    return DTANS_OK;
+}
+
+dtans_status dtans_csr_spmv(dtans_csr *h, const void *x, void *y, double alpha, double beta,
+                            void *stream) {
+    return dtans_csr_spmm(h, 1, x, 1, y, 1, alpha, beta, stream);
+}
+
+int64_t dtans_csr_bytes(const dtans_csr *h) { return h ? h->bytes : 0; }
+
+void dtans_csr_destroy(dtans_csr *h) {
+    if (!h) return;
+    if (h->partial) (void)hipFree(h->partial);
+    delete h;
+}
+
+dtans_status dtans_autotune(int64_t, int64_t, int64_t, const int32_t *, const int32_t *, const void *,
+                            dtans_dtype, int32_t, double, dtans_encode_opts *, double *) {
+    return set_err(DTANS_EUNSUPPORTED, "autotuner not built yet");
+}
+
+}  // extern "C"

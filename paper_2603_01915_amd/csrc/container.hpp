@@ -1,0 +1,83 @@
+// Host-side CSR-dtANS container of the library: the encoded matrix as it is
+// written to / read from a file and uploaded to the GPU.
+#pragma once
+
+#include <stdint.h>
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "dtans_core.hpp"
+
+namespace dtans {
+
+enum : uint32_t { kF32 = 1, kF64 = 2 };
+enum : uint32_t { kLayoutRow = 1, kLayoutNnz = 2 };
+
+// One alphabet's coding table over K slots (Sec. III-D, IV-C): the symbol,
+// digit and base of every slot; flags bit 0 = slot used, bit 1 = escape.
+struct Table {
+    std::array<uint64_t, kSlots> sym{};
+    std::array<uint8_t, kSlots> digit{};
+    std::array<uint16_t, kSlots> base{};  // 1..256, 0 when unused
+    std::array<uint8_t, kSlots> flags{};
+    int symbols = 0;        // table symbols without the escape
+    bool has_escape = false;
+    double entropy = 0, cross_entropy = 0;  // Eq. 1 / Eq. 2 over the encoded symbols
+};
+
+struct Container {
+    uint32_t dtype = kF64, layout = kLayoutRow, lane_nnz = 0;
+    int64_t m = 0, n = 0, nnz = 0, num_lanes = 0, num_waves = 0;
+    uint64_t seed = 1;
+    Table dtab, vtab;
+    std::vector<int32_t> row_ptr;                 // m + 1
+    std::vector<uint64_t> word_off, escd_off, escv_off;  // num_waves + 1 each
+    std::vector<uint32_t> words;
+    std::vector<uint32_t> escd;
+    std::vector<uint64_t> escv;                   // FP32 values in the low 32 bits
+
+    size_t value_bytes() const { return dtype == kF64 ? 8 : 4; }
+    // nonzero range of lane l
+    void lane_range(int64_t l, int64_t &g0, int64_t &cnt) const {
+        if (layout == kLayoutRow) {
+            g0 = row_ptr[l];
+            cnt = (int64_t)row_ptr[l + 1] - row_ptr[l];
+        } else {
+            g0 = l * (int64_t)lane_nnz;
+            int64_t e = g0 + lane_nnz;
+            cnt = (e < nnz ? e : nnz) - g0;
+        }
+    }
+};
+
+struct EncodeParams {
+    uint32_t layout = kLayoutRow;
+    uint32_t lane_nnz = 0;
+    uint64_t seed = 1;
+    int threads = 0;  // 0 = hardware concurrency
+};
+
+// All functions return an empty string on success or an error message whose
+// first word is the error class ("EINVAL: ...", "ERANGE: ...", ...).
+std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                       const int32_t *col, const void *vals, uint32_t dtype,
+                       const EncodeParams &p, Container &out);
+std::string save_container(const Container &c, const std::string &path);
+std::string load_container(const std::string &path, Container &c);
+// Full host decode with the kernels' integer arithmetic; fills col / vals
+// (value bits, FP32 in the low half) when non-null.
+std::string host_decode(const Container &c, int32_t *col, uint64_t *vals);
+
+// Layout NNZ metadata derived from row_ptr: the row holding each lane's first
+// nonzero (lane 0 starts at row 0 so that leading empty rows are its own), and
+// the rows that span more than one lane with their first and last lane.
+void nnz_layout_meta(const Container &c, std::vector<int32_t> &lane_row,
+                     std::vector<int32_t> &split_row, std::vector<int32_t> &split_first,
+                     std::vector<int32_t> &split_last);
+
+// GPU table: one 64-bit entry per slot (see dtans_core.hpp) + one value per slot
+void gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values);
+
+}  // namespace dtans

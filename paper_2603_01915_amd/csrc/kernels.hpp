@@ -1,0 +1,73 @@
+// Launch interface between the C ABI and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtans {
+
+// Device view of one encoded matrix (all pointers are device pointers).
+struct DevMat {
+    const uint64_t *tab;     // K table entries (see dtans_core.hpp)
+    const void *tabval;      // K values (float or double)
+    const int32_t *row_ptr;  // m + 1
+    const uint64_t *woff, *doff, *voff;  // per-wave word / escape offsets
+    const uint32_t *words;
+    const uint32_t *escd;
+    const void *escv;        // raw escaped values (float or double)
+    const int32_t *lane_row; // layout NNZ: row holding each lane's first nonzero
+    const int32_t *split_row, *split_first, *split_last;  // layout NNZ
+    int64_t m, n, nnz, num_lanes, num_waves, nsplit;
+    int32_t lane_nnz, layout;  // layout: 1 row per lane, 2 nonzeros per lane
+};
+
+struct Launch {
+    int waves_per_wg;  // 1..16
+    int grid;          // number of workgroups
+};
+
+// y = alpha*A*x + beta*y; k columns of X/Y (k = 1: SpMV); partial: layout NNZ
+// scratch of 2 * num_lanes * k doubles.
+hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, double alpha, double beta, double *partial, Launch L,
+                       hipStream_t st);
+// dX = alpha*A^T*dY + beta*dX via decode-and-scatter
+hipError_t launch_spmm_t(const DevMat &a, bool f64, int k, const void *dY, int64_t lddy, void *dX,
+                         int64_t lddx, double alpha, double beta, Launch L, hipStream_t st);
+// decode to CSR (col / raw value bits); row_ptr copied by the caller
+hipError_t launch_decode(const DevMat &a, bool f64, int32_t *col, void *vals, Launch L,
+                         hipStream_t st);
+
+// many matrices (same dtype, layout ROW) in one persistent launch
+struct BatchTask {  // a contiguous run of waves of one matrix for one workgroup
+    int32_t mat;
+    int32_t first_wave;
+    int32_t num_waves;
+    int32_t pad;
+};
+constexpr int kMaxBatch = 128;
+struct BatchDev {
+    const DevMat *mats;      // device array of matrix views
+    const BatchTask *tasks;  // device array, grouped per workgroup
+    const int32_t *wg_task;  // device, grid + 1 offsets into tasks
+    // x / y device pointers of each matrix, passed by value with the launch
+    const void *xs[kMaxBatch];
+    void *ys[kMaxBatch];
+};
+hipError_t launch_batch(const BatchDev &b, bool f64, double alpha, double beta, Launch L,
+                        hipStream_t st);
+
+// plain CSR baseline.  variant 1: G lanes per row; variant 2: lane_nnz
+// nonzeros per lane with partials + fix-up (lane_row, split_* as for DevMat).
+struct CsrDev {
+    const int32_t *row_ptr, *col;
+    const void *val;
+    const int32_t *lane_row, *split_row, *split_first, *split_last;
+    int64_t m, n, nnz, num_lanes, nsplit;
+    int32_t variant, group, lane_nnz;
+};
+hipError_t launch_csr(const CsrDev &c, bool f64, int k, const void *X, int64_t ldx, void *Y,
+                      int64_t ldy, double alpha, double beta, double *partial, int num_cus,
+                      hipStream_t st);
+
+}  // namespace dtans

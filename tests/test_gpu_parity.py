@@ -1,0 +1,253 @@
+"""GPU parity: the HIP kernels against the oracle, through the C ABI.
+
+* decoding is bit-exact against the original CSR, for containers written by
+  the library and by the oracle's independent encoder;
+* y = alpha*A*x + beta*y is within 1e-12 (FP64) / 2e-6 (FP32) of the oracle's
+  FP64 product, relative to (|A||x|)_i;
+* SpMM, the transposed product, the multi-matrix launch and the plain-CSR
+  baseline are checked the same way.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from gpu_common import TOL, check_spmv, need_gpu, progress, rel_error
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_01915_amd")
+
+LAYOUTS = [("row", 0), ("nnz", 32), ("nnz", 128)]
+
+
+def adversarial(seed=3, n=5000):
+    rng = np.random.default_rng(seed)
+    rows = [[], [7], [1, 2], [0, 0, 3], [], list(range(0, n, 2)), [n - 1], [], [5, 5, 5, 5, 5],
+            list(range(100, 113))]
+    rows += [sorted(rng.choice(n, size=rng.integers(0, 12), replace=False)) for _ in range(700)]
+    rows += [[]] * 70  # a run of empty rows longer than a wave
+    rows += [sorted(rng.choice(n, size=rng.integers(1, 4), replace=False)) for _ in range(200)]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], np.int64).astype(np.int32)
+    v = rng.standard_normal(len(ci))  # mostly distinct values: value escapes
+    v[::5] = 0.5
+    return rp.astype(np.int32), ci, v, n
+
+
+def small_cases():
+    rp, ci, v = workloads.band(m=1000, per_row=16, half=256)
+    yield "band1000", rp, ci, v, 1000
+    rp, ci, v = workloads.stencil27(12)
+    yield "stencil12", rp, ci, v, 12 ** 3
+    rp, ci, v = workloads.rmat(scale=11, edge_factor=16)
+    yield "rmat11", rp, ci, v, 2 ** 11
+    rp, ci, v = workloads.pruned_weight(rows=300, cols=256)
+    yield "pruned300", rp, ci, v, 256
+    rp, ci, v, n = adversarial()
+    yield "adversarial", rp, ci, v, n
+
+
+CASES = list(small_cases())
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_decode_bit_exact(case, layout, T, dtype):
+    torch = need_gpu()
+    name, rp, ci, v, n = CASES[case]
+    v = v.astype(dtype)
+    progress("decode %s %s T=%d %s" % (name, layout, T, dtype.__name__))
+    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T)
+    r2, c2, v2 = A.decode_csr()
+    torch.cuda.synchronize()
+    assert np.array_equal(r2.cpu().numpy(), rp)
+    assert np.array_equal(c2.cpu().numpy(), ci)
+    assert np.array_equal(v2.cpu().numpy().view(np.uint8), v.view(np.uint8))
+
+
+@pytest.mark.parametrize("layout,T", [(1, 0), (2, 32), (2, 12)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_decode_oracle_containers(tmp_path, layout, T, dtype):
+    """The GPU decodes containers written by the oracle's own encoder."""
+    torch = need_gpu()
+    for name, rp, ci, v, n in CASES:
+        v = v.astype(dtype)
+        progress("oracle container %s layout=%d T=%d %s" % (name, layout, T, dtype.__name__))
+        path = str(tmp_path / (name + ".dtans"))
+        oracle.encode(path, len(rp) - 1, n, rp, ci, v, layout=layout, lane_nnz=T, seed=11)
+        A = P.Matrix.load(path)
+        r2, c2, v2 = A.decode_csr()
+        torch.cuda.synchronize()
+        assert np.array_equal(c2.cpu().numpy(), ci)
+        assert np.array_equal(v2.cpu().numpy().view(np.uint8), v.view(np.uint8))
+        x = workloads.vector(n, 9, dtype)
+        y = A.spmv(torch.from_numpy(x).cuda())
+        check_spmv(y.cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_spmv_parity(case, layout, T, dtype):
+    torch = need_gpu()
+    name, rp, ci, v, n = CASES[case]
+    v = v.astype(dtype)
+    m = len(rp) - 1
+    progress("spmv %s %s T=%d %s" % (name, layout, T, dtype.__name__))
+    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T)
+    x = workloads.vector(n, 7, dtype)
+    xd = torch.from_numpy(x).cuda()
+    y = A.spmv(xd)
+    check_spmv(y.cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+    # alpha, beta with an existing y; and beta = 0 over a NaN-filled y
+    y0 = workloads.vector(m, 8, dtype)
+    yd = torch.from_numpy(y0.copy()).cuda()
+    A.spmv(xd, yd, alpha=-0.75, beta=1.5)
+    check_spmv(yd.cpu().numpy(), rp, ci, v, x, y0, -0.75, 1.5, dtype)
+    yn = torch.full((m,), float("nan"), dtype=yd.dtype, device="cuda")
+    A.spmv(xd, yn, alpha=2.0, beta=0.0)
+    check_spmv(yn.cpu().numpy(), rp, ci, v, x, None, 2.0, 0.0, dtype)
+    # repeated calls give the same result bit for bit (no atomics in SpMV)
+    y2 = A.spmv(xd)
+    assert torch.equal(y, y2)
+
+
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("k", [1, 3, 8, 32, 37])
+def test_spmm_parity(layout, T, dtype, k):
+    torch = need_gpu()
+    rp, ci, v = workloads.pruned_weight(rows=400, cols=300)
+    v = v.astype(dtype)
+    m, n = 400, 300
+    progress("spmm %s T=%d %s k=%d" % (layout, T, dtype.__name__, k))
+    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T)
+    X = workloads.vector(n, 4, dtype, k=k)
+    Y = A.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yref = oracle.spmm(rp, ci, v, X)
+    for c in range(k):
+        scale = oracle.absmv(rp, ci, v, X[:, c])
+        assert rel_error(Y[:, c], Yref[:, c], scale) <= TOL[dtype]
+    # strided X / Y (leading dimension > k) and beta
+    Xs = torch.zeros((n, k + 5), dtype=A.torch_dtype, device="cuda")
+    Xs[:, :k] = torch.from_numpy(X).cuda()
+    Y0 = workloads.vector(m, 5, dtype, k=k)
+    Ys = torch.zeros((m, k + 3), dtype=A.torch_dtype, device="cuda")
+    Ys[:, :k] = torch.from_numpy(Y0).cuda()
+    A.spmm(Xs[:, :k], Ys[:, :k], alpha=0.5, beta=-1.0)
+    Yb = Ys[:, :k].cpu().numpy()
+    Yref = oracle.spmm(rp, ci, v, X, Y0, alpha=0.5, beta=-1.0)
+    for c in range(k):
+        scale = 0.5 * oracle.absmv(rp, ci, v, X[:, c]) + np.abs(Y0[:, c].astype(np.float64))
+        assert rel_error(Yb[:, c], Yref[:, c], scale) <= TOL[dtype]
+    assert torch.count_nonzero(Ys[:, k:]) == 0
+
+
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("k", [1, 16])
+def test_spmm_t_parity(layout, T, dtype, k):
+    torch = need_gpu()
+    for name, rp, ci, v, n in CASES:
+        v = v.astype(dtype)
+        m = len(rp) - 1
+        progress("spmm_t %s %s T=%d %s k=%d" % (name, layout, T, dtype.__name__, k))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T)
+        dY = workloads.vector(m, 6, dtype, k=k)
+        dX0 = workloads.vector(n, 3, dtype, k=k)
+        dX = torch.from_numpy(dX0.copy()).cuda()
+        A.spmm_t(torch.from_numpy(dY).cuda(), dX, alpha=1.25, beta=0.5)
+        out = dX.cpu().numpy()
+        At = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
+        At.sort_indices()
+        for c in range(k):
+            ref = oracle.spmtv(rp, ci, v, n, dY[:, c], dX0[:, c], alpha=1.25, beta=0.5)
+            scale = 1.25 * oracle.absmv(At.indptr, At.indices, At.data, dY[:, c]) + \
+                0.5 * np.abs(dX0[:, c].astype(np.float64))
+            assert rel_error(out[:, c], ref, scale) <= TOL[dtype], (name, c)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_csr_baseline_parity(variant, dtype):
+    torch = need_gpu()
+    for name, rp, ci, v, n in CASES:
+        v = v.astype(dtype)
+        progress("csr baseline v%d %s %s" % (variant, name, dtype.__name__))
+        B = P.CsrBaseline(rp, ci, v, n, variant=variant)
+        x = workloads.vector(n, 7, dtype)
+        y = B.spmv(torch.from_numpy(x).cuda())
+        check_spmv(y.cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+        X = workloads.vector(n, 4, dtype, k=8)
+        Y = B.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+        for c in range(8):
+            check_spmv(Y[:, c], rp, ci, v, X[:, c], None, 1.0, 0.0, dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batch_matches_single(dtype):
+    torch = need_gpu()
+    mats = workloads.batch(count=12, lo_exp=6, hi_exp=12, half=64)
+    progress("batch of %d %s" % (len(mats), dtype.__name__))
+    enc, xs, refs = [], [], []
+    for i, (m, (rp, ci, v)) in enumerate(mats):
+        v = v.astype(dtype)
+        enc.append(P.Matrix.from_csr(rp, ci, v, m, layout="row"))
+        x = workloads.vector(m, 100 + i, dtype)
+        xs.append(torch.from_numpy(x).cuda())
+        refs.append((rp, ci, v, x))
+    b = P.Batch(enc)
+    ys = b.spmv(xs)
+    for (rp, ci, v, x), y, A, xd in zip(refs, ys, enc, xs):
+        check_spmv(y.cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+        assert torch.equal(y, A.spmv(xd))  # same kernel body, same order
+    ys2 = [torch.ones_like(y) for y in ys]
+    b.spmv(xs, ys2, alpha=2.0, beta=-1.0)
+    for (rp, ci, v, x), y in zip(refs, ys2):
+        check_spmv(y.cpu().numpy(), rp, ci, v, x, np.ones(len(rp) - 1, dtype), 2.0, -1.0, dtype)
+
+
+def test_empty_and_degenerate():
+    torch = need_gpu()
+    for layout, T in LAYOUTS:
+        progress("degenerate %s %d" % (layout, T))
+        # all rows empty
+        A = P.Matrix.from_csr(np.zeros(65, np.int32), np.zeros(0, np.int32), np.zeros(0), 10,
+                              layout=layout, lane_nnz=T)
+        y = torch.full((64,), 3.0, dtype=torch.float64, device="cuda")
+        A.spmv(torch.ones(10, dtype=torch.float64, device="cuda"), y, beta=0.5)
+        assert torch.all(y == 1.5)
+        # a single nonzero
+        A = P.Matrix.from_csr(np.array([0, 0, 1, 1], np.int32), np.array([4], np.int32),
+                              np.array([2.5]), 6, layout=layout, lane_nnz=T)
+        y = A.spmv(torch.arange(6, dtype=torch.float64, device="cuda"))
+        assert y.tolist() == [0.0, 10.0, 0.0]
+        # one long row among empty rows
+        rp = np.array([0, 0, 5000, 5000, 5000], np.int32)
+        ci = np.arange(5000, dtype=np.int32)
+        v = np.full(5000, 0.25)
+        A = P.Matrix.from_csr(rp, ci, v, 5000, layout=layout, lane_nnz=T)
+        y = A.spmv(torch.ones(5000, dtype=torch.float64, device="cuda"))
+        assert y.tolist() == [0.0, 1250.0, 0.0, 0.0]
+
+
+def test_launch_shapes_agree():
+    """Every launch shape gives the bit-identical y (the lane work and the
+    summation order do not depend on the grid)."""
+    torch = need_gpu()
+    rp, ci, v = workloads.stencil27(20)
+    n = 20 ** 3
+    x = torch.from_numpy(workloads.vector(n, 2)).cuda()
+    ref = None
+    for wpw, wgcu in ((1, 1), (4, 2), (14, 2), (16, 1), (7, 3)):
+        progress("launch shape %d x %d" % (wpw, wgcu))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout="row", waves_per_wg=wpw, wg_per_cu=wgcu)
+        y = A.spmv(x)
+        if ref is None:
+            ref = y
+            check_spmv(y.cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, np.float64)
+        assert torch.equal(y, ref)

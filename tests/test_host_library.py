@@ -1,0 +1,199 @@
+"""Host side of libdtans, no GPU needed: the library's encoder is checked by the
+oracle's decoder (cross-decode), the library's verifying loader accepts the
+oracle's containers, error codes, options, statistics and the C ABI exports."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from oracle import container
+
+P = pytest.importorskip("paper_2603_01915_amd")
+from paper_2603_01915_amd import _lib  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rand_csr(m, n, dens, seed, dtype=np.float64, pool=None):
+    rng = np.random.default_rng(seed)
+    A = sp.random(m, n, density=dens, format="csr", random_state=rng)
+    A.sort_indices()
+    v = rng.standard_normal(A.nnz) if pool is None else rng.choice(rng.standard_normal(pool), A.nnz)
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), v.astype(dtype)
+
+
+def test_header_symbols_exported():
+    """Every function declared in include/dtans.h is exported by libdtans.so."""
+    text = open(os.path.join(ROOT, "include", "dtans.h")).read()
+    names = set(re.findall(r"^\s*(?:dtans_status|void|const char \*|int64_t)\s*\*?\s*(dtans_\w+)\s*\(",
+                           text, re.M))
+    assert len(names) == 23
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(_lib.SIGNATURES)
+    assert P.version().startswith("dtans")
+
+
+LAYOUTS = [("row", 0), ("nnz", 4), ("nnz", 32), ("nnz", 100)]
+
+
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_library_encoder_cross_decoded_by_oracle(tmp_path, layout, T, dtype):
+    rp, ci, v = rand_csr(700, 500, 0.02, 1, dtype, pool=300)
+    A = P.Matrix.from_csr(rp, ci, v, 500, layout=layout, lane_nnz=T)
+    path = str(tmp_path / "lib.dtans")
+    A.save(path)
+    r2, c2, v2 = oracle.decode(path)
+    assert np.array_equal(r2, rp) and np.array_equal(c2, ci)
+    assert np.array_equal(v2.view(np.uint8), v.view(np.uint8))
+    # and the Python big-integer container codec agrees too
+    _, c3, v3 = container.decode(container.read(path))
+    assert np.array_equal(c3, ci) and np.array_equal(v3.view(np.uint8), v.view(np.uint8))
+
+
+@pytest.mark.parametrize("layout,T", [(1, 0), (2, 8), (2, 64)])
+def test_library_loads_oracle_containers(tmp_path, layout, T):
+    rp, ci, v = rand_csr(300, 200, 0.05, 2, pool=50)
+    path = str(tmp_path / "or.dtans")
+    oracle.encode(path, 300, 200, rp, ci, v, layout=layout, lane_nnz=T)
+    A = P.Matrix.load(path)
+    inf = A.info()
+    assert inf["layout"] == layout and inf["nnz"] == len(ci)
+    # saving it again reproduces the same bytes
+    p2 = str(tmp_path / "again.dtans")
+    A.save(p2)
+    assert open(path, "rb").read() == open(p2, "rb").read()
+
+
+def test_adversarial_cross_decode(tmp_path):
+    rng = np.random.default_rng(3)
+    n = 2 ** 31 - 1
+    rows = [[], [7], [1, 2], [0, 0, 3], [], [2 ** 30, 2 ** 31 - 2], [4999], [], [5, 5, 5, 5, 5],
+            list(range(100, 113)), list(range(0, 20000, 3))]
+    rows += [sorted(rng.choice(10 ** 6, size=rng.integers(0, 9), replace=False)) for _ in range(300)]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], np.int64).astype(np.int32)
+    v = rng.standard_normal(len(ci))
+    v[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, 5e-324]
+    for layout, T in LAYOUTS:
+        A = P.Matrix.from_csr(rp.astype(np.int32), ci, v, n, layout=layout, lane_nnz=T)
+        path = str(tmp_path / ("adv_%s_%d.dtans" % (layout, T)))
+        A.save(path)
+        r2, c2, v2 = oracle.decode(path)
+        assert np.array_equal(c2, ci) and np.array_equal(v2.view(np.uint8), v.view(np.uint8))
+        assert P.Matrix.load(path).nnz == len(ci)
+
+
+def test_empty_and_tiny(tmp_path):
+    for m, n in ((0, 5), (5, 5), (1, 1)):
+        rp = np.zeros(m + 1, np.int32)
+        A = P.Matrix.from_csr(rp, np.zeros(0, np.int32), np.zeros(0), n)
+        assert A.info()["words"] == 0
+        path = str(tmp_path / "e.dtans")
+        A.save(path)
+        r2, c2, _ = oracle.decode(path)
+        assert np.array_equal(r2, rp) and len(c2) == 0
+
+
+def test_error_codes():
+    rp = np.array([0, 2, 3], np.int32)
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.from_csr(rp, np.array([3, 1, 0], np.int32), np.ones(3), 5)
+    assert e.value.status == _lib.EUNSORTED
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.from_csr(rp, np.array([1, 9, 0], np.int32), np.ones(3), 5)
+    assert e.value.status == _lib.ERANGE
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.from_csr(np.array([0, 2, 4], np.int32), np.array([1, 2, 0], np.int32), np.ones(3), 5)
+    assert e.value.status == _lib.EINVAL
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.from_csr(rp, np.array([1, 2, 0], np.int32), np.ones(3), 5, layout="nnz", lane_nnz=6)
+    assert e.value.status == _lib.EINVAL
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.load("/nonexistent/file.dtans")
+    assert e.value.status == _lib.EIO
+
+
+def test_sort_rows_option(tmp_path):
+    rp = np.array([0, 3, 5], np.int32)
+    ci = np.array([4, 0, 2, 3, 1], np.int32)
+    v = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    A = P.Matrix.from_csr(rp, ci, v, 6, sort_rows=True)
+    path = str(tmp_path / "s.dtans")
+    A.save(path)
+    _, c2, v2 = oracle.decode(path)
+    assert list(c2) == [0, 2, 4, 1, 3] and list(v2) == [2.0, 3.0, 1.0, 5.0, 4.0]
+
+
+def test_corrupted_container_rejected(tmp_path):
+    rp, ci, v = rand_csr(200, 100, 0.05, 4, pool=20)
+    path = str(tmp_path / "c.dtans")
+    P.Matrix.from_csr(rp, ci, v, 100).save(path)
+    data = bytearray(open(path, "rb").read())
+    for off in (400, len(data) // 2, len(data) - 2):
+        bad = bytearray(data)
+        bad[off] ^= 0x01
+        open(path, "wb").write(bad)
+        with pytest.raises(P.DtansError) as e:
+            P.Matrix.load(path)
+        assert e.value.status == _lib.ECORRUPT
+    # consistent checksum but one word too few in a wave: the verifying
+    # decode notices the mismatch
+    open(path, "wb").write(data)
+    c = container.read(path)
+    end0 = int(c.word_off[1])
+    c.words = np.delete(c.words, end0 - 1)
+    c.word_off = (c.word_off.astype(np.int64) - np.r_[0, np.ones(len(c.word_off) - 1, np.int64)]).astype(np.uint64)
+    container.write(path, c)
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.load(path)
+    assert e.value.status == _lib.ECORRUPT
+
+
+def test_info_statistics():
+    rp, ci, v = workloads.stencil27(16)
+    A = P.Matrix.from_csr(rp, ci, v, 16 ** 3, layout="row")
+    inf = A.info()
+    assert inf["csr_bytes"] == 4 * (16 ** 3 + 1) + 12 * len(ci)
+    assert inf["coo_bytes"] == 16 * len(ci)
+    assert inf["table_bytes"] == 4096 * 16
+    assert inf["stream_bytes"] == 4 * inf["words"] + 4 * inf["esc_delta"] + 8 * inf["esc_value"]
+    assert inf["total_bytes"] < inf["csr_bytes"]
+    # every symbol costs at least log2(K/M) = 4 bits: at least 1 byte per nonzero
+    assert inf["stream_bytes"] >= len(ci)
+    # the value alphabet has at most 216 distinct stencil values, all in the table
+    assert inf["value_symbols"] <= 216 and inf["esc_value"] == 0
+    assert 0 < inf["value_entropy"] <= np.log2(216) + 1e-9
+    assert inf["value_cross_entropy"] >= inf["value_entropy"] - 1e-9
+    # the first delta of every row is its raw column (paper mode): escapes
+    assert inf["esc_delta"] > 0
+
+
+def test_all_bases_256_word_count():
+    # one delta symbol and one value symbol: both get multiplicity 256, every
+    # check extracts, and a lane of S segments stores S + 2 words (Sec. IV-D)
+    S = 9
+    m = 64
+    rows = [list(range(1, 4 * S + 1))] * m
+    rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
+    ci = np.array([c for r in rows for c in r], np.int32)
+    A = P.Matrix.from_csr(rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row")
+    assert A.info()["words"] == m * (S + 2)
+
+
+def test_compression_closed_form_bound():
+    # at least 4 bits per symbol: compression vs FP64 CSR is at most 12x
+    # (Sec. V-A prints 11.77x as its best), vs FP32 CSR at most 8x (7.86x)
+    rp, ci, v = workloads.stencil27(24)
+    for dt, bound in ((np.float64, 12.0), (np.float32, 8.0)):
+        A = P.Matrix.from_csr(rp, ci, v.astype(dt), 24 ** 3)
+        inf = A.info()
+        assert inf["csr_bytes"] / inf["stream_bytes"] <= bound
