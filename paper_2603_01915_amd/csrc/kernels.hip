@@ -173,62 +173,95 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     const int S = (int)((cnt + 3) >> 2);
     const int Smax = wave_max(S);
 
-    const uint32_t *__restrict__ W = a.words;
-    uint64_t pos = a.woff[slice], dpos = a.doff[slice], vpos = a.voff[slice];
-    uint32_t w1 = 0, w2 = 0, w3 = 0;
+    // per-wave stream bases are uniform; offsets into them stay 32-bit and
+    // uniform (popcounts of ballots), so the compiler keeps them in SGPRs
+    const uint32_t *__restrict__ W = a.words + a.woff[slice];
+    const uint32_t *__restrict__ ED = a.escd + a.doff[slice];
+    const VT *__restrict__ EV = (const VT *)a.escv + a.voff[slice];
+    uint32_t pos, dpos = 0, vpos = 0;
+    uint32_t w1, w2, w3;
     {
+        // lanes without a stream read a neighbouring word (buffers are padded)
         const uint64_t mk = __ballot(S > 0);
         const uint32_t pre = lane_prefix(mk), c = (uint32_t)__popcll(mk);
-        if (S > 0) {
-            w1 = W[pos + pre];
-            w2 = W[pos + c + pre];
-            w3 = W[pos + 2 * c + pre];
-        }
-        pos += 3 * c;
+        w1 = W[pre];
+        w2 = W[c + pre];
+        w3 = W[2 * c + pre];
+        pos = 3 * c;
     }
     uint32_t d = 0, r = 1, col = 0;
     int64_t g = g0;
     for (int j = 0; j < Smax; ++j) {
         const bool act = j < S;
         const bool more = j + 1 < S;
-        const int64_t rem = cnt - 4 * (int64_t)j;
+        const int rem = (int)cnt - 4 * j;
         uint32_t sl[8];
         unpack8(w1, w2, w3, sl);
         uint64_t e[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) e[k] = tab[sl[k]];
         VT v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = tval[sl[2 * k + 1]];
+        // The next segment's words first, so that their loads are in flight
+        // while this segment's escapes and x gathers are served.  Loads are
+        // issued by every lane and the extracted word selected afterwards;
+        // lanes that do not load read a neighbouring word of the stream.
+        if (j + 1 < Smax) {
+            uint32_t D, Rm1, x1, x2;
+            group4((uint32_t)(e[0] >> 32) & 0xffffu, (uint32_t)(e[1] >> 48),
+                   (uint32_t)(e[2] >> 32) & 0xffffu, (uint32_t)(e[3] >> 48), D, Rm1);
+            const bool ext1 = append_and_check(d, r, D, Rm1, x1);
+            group4((uint32_t)(e[4] >> 32) & 0xffffu, (uint32_t)(e[5] >> 48),
+                   (uint32_t)(e[6] >> 32) & 0xffffu, (uint32_t)(e[7] >> 48), D, Rm1);
+            const bool ext2 = append_and_check(d, r, D, Rm1, x2);
+            const uint64_t m1 = __ballot(more && !ext1);
+            const uint64_t m2 = __ballot(more && !ext2);
+            const uint64_t m3 = __ballot(more);
+            const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
+            const uint32_t l1 = W[pos + lane_prefix(m1)];
+            const uint32_t l2 = W[pos + c1 + lane_prefix(m2)];
+            const uint32_t l3 = W[pos + c1 + c2 + lane_prefix(m3)];
+            pos += c1 + c2 + (uint32_t)__popcll(m3);
+            w1 = ext1 ? x1 : l1;
+            w2 = ext2 ? x2 : l2;
+            w3 = l3;
+        }
         uint32_t dl[4];
-        uint32_t escbits = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[k] = tval[sl[2 * k + 1]];
-            const uint32_t lo_d = (uint32_t)e[2 * k], lo_v = (uint32_t)e[2 * k + 1];
-            dl[k] = lo_d & (kDeltaLimit - 1);
-            const bool real = act && k < rem;
-            escbits |= (real && (lo_d >> 31)) ? (1u << k) : 0u;
-            escbits |= (real && ((lo_v >> 30) & 1u)) ? (16u << k) : 0u;
-        }
-        if (__ballot(escbits != 0)) {  // wave-uniform: some lane hit an escape
+        for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k] & (kDeltaLimit - 1);
+        // escape flags: bit 31 of a delta slot's word, bit 30 of a value
+        // slot's word.  Padding symbols are never escapes, so only lanes past
+        // their last segment need masking.
+        const uint32_t escd_any = (uint32_t)e[0] | (uint32_t)e[2] | (uint32_t)e[4] | (uint32_t)e[6];
+        const uint32_t escv_any = (uint32_t)e[1] | (uint32_t)e[3] | (uint32_t)e[5] | (uint32_t)e[7];
+        if (__ballot(act && (((escd_any >> 1) | escv_any) & (1u << 30)))) {  // wave-uniform
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const bool f = (escbits >> k) & 1u;
+                const bool f = act && k < rem && ((uint32_t)e[2 * k] >> 31);
                 const uint64_t mk = __ballot(f);
-                if (f) dl[k] = a.escd[dpos + lane_prefix(mk)];
-                dpos += __popcll(mk);
+                if (f) dl[k] = ED[dpos + lane_prefix(mk)];
+                dpos += (uint32_t)__popcll(mk);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const bool f = (escbits >> (4 + k)) & 1u;
+                const bool f = act && k < rem && (((uint32_t)e[2 * k + 1] >> 30) & 1u);
                 const uint64_t mk = __ballot(f);
-                if (f) v[k] = load_value<VT>(a.escv, vpos + lane_prefix(mk));
-                vpos += __popcll(mk);
+                if (f) v[k] = EV[vpos + lane_prefix(mk)];
+                vpos += (uint32_t)__popcll(mk);
             }
         }
+        if (LAYOUT == 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (act && k < rem) {
-                if (LAYOUT == 2) {
+            for (int k = 0; k < 4; ++k) {
+                col += dl[k];
+                if (act && k < rem) sink.nz(g + k, row, col, v[k]);
+            }
+            g += 4;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (act && k < rem) {
                     while (g >= row_end) {  // rows ending before this nonzero
                         sink.row_done(row, row_beg < g0 ? kHead : kComplete);
                         col = 0;
@@ -236,32 +269,11 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                         row_beg = row_end;
                         row_end = a.row_ptr[row + 1];
                     }
+                    col += dl[k];
+                    sink.nz(g, row, col, v[k]);
+                    ++g;
                 }
-                col += dl[k];
-                sink.nz(g, row, col, v[k]);
-                ++g;
             }
-        }
-        if (j + 1 < Smax) {
-            uint32_t D, Rm1, nw1 = 0, nw2 = 0, nw3 = 0;
-            group4((uint32_t)(e[0] >> 32) & 0xffffu, (uint32_t)(e[1] >> 48),
-                   (uint32_t)(e[2] >> 32) & 0xffffu, (uint32_t)(e[3] >> 48), D, Rm1);
-            bool ld = more && !append_and_check(d, r, D, Rm1, nw1);
-            uint64_t mk = __ballot(ld);
-            if (ld) nw1 = W[pos + lane_prefix(mk)];
-            pos += __popcll(mk);
-            group4((uint32_t)(e[4] >> 32) & 0xffffu, (uint32_t)(e[5] >> 48),
-                   (uint32_t)(e[6] >> 32) & 0xffffu, (uint32_t)(e[7] >> 48), D, Rm1);
-            ld = more && !append_and_check(d, r, D, Rm1, nw2);
-            mk = __ballot(ld);
-            if (ld) nw2 = W[pos + lane_prefix(mk)];
-            pos += __popcll(mk);
-            mk = __ballot(more);
-            if (more) nw3 = W[pos + lane_prefix(mk)];
-            pos += __popcll(mk);
-            w1 = nw1;
-            w2 = nw2;
-            w3 = nw3;
         }
     }
     if (!live) return;
@@ -299,7 +311,9 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t total = (int64_t)gridDim.x * wpb;
-    const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * wpb + threadIdx.x / kWave;
+    // the wave index is uniform; readfirstlane lets the compiler know it
+    const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * wpb +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t s0 = gw * a.num_waves / total, s1 = (gw + 1) * a.num_waves / total;
     for (int64_t s = s0; s < s1; ++s) {
         Sink sink(sp, s * kWave + lane);
@@ -338,7 +352,7 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const int wib = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), wpb = blockDim.x / kWave;
     const int t0 = b.wg_task[blockIdx.x], t1 = b.wg_task[blockIdx.x + 1];
     int cur = -1;
     for (int t = t0; t < t1; ++t) {
