@@ -158,8 +158,13 @@ dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_
                               void *stream);
 
 /*
- * Many matrices in one persistent launch.  All matrices share the dtype.
- * xs[i] / ys[i] are device pointers for matrix i (host array of pointers).
+ * Many matrices (at most 128, same dtype, ROW layout) in one persistent
+ * launch: workgroups walk contiguous, cost-balanced runs of encoded waves and
+ * restage their LDS tables only when the matrix changes.  xs[i] / ys[i] are
+ * device pointers for matrix i (host array of pointers, read during the
+ * call).  The batch keeps a device table of these pointers that each call
+ * rewrites on its stream, so calls on one batch must not run concurrently on
+ * different streams.  The batch references the matrices; they must outlive it.
  */
 dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_batch **out);
 dtans_status dtans_batch_spmv(dtans_batch *batch, const void *const *xs, void *const *ys,

@@ -119,10 +119,11 @@ Launch plan_launch(const dtans_matrix *h) {
     const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
     const int lds_per_cu = 160 * 1024;
     // LDS admits lds_per_cu / table_bytes workgroups per CU (2 for FP64, 3 for
-    // FP32); the decode kernels are register-limited to 7 waves per SIMD, so
-    // 14 (FP64) or 9 (FP32) waves per workgroup fill 28 / 27 of 28 slots
+    // FP32).  The row-layout SpMV kernels fit 8 waves per SIMD (32 per CU),
+    // the nonzero-balanced ones 7 (28 per CU); split those slots evenly.
     int wgcu = h->wg_per_cu > 0 ? h->wg_per_cu : std::max(1, lds_per_cu / table_bytes);
-    int wpw = h->waves_per_wg > 0 ? h->waves_per_wg : (f64 ? 14 : 9);
+    const int slots = h->c.layout == kLayoutRow ? 32 : 28;
+    int wpw = h->waves_per_wg > 0 ? h->waves_per_wg : std::min(16, slots / wgcu);
     Launch L;
     L.waves_per_wg = wpw;
     int64_t need = (h->c.num_waves + wpw - 1) / wpw;
@@ -396,6 +397,7 @@ dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx
     const Container &c = mat->c;
     if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
     if (ldx < k || ldy < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
+    if (ldx >= (1ll << 31) || ldy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
     if ((c.m > 0 && !Y) || (c.n > 0 && c.nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
     if (c.layout == kLayoutNnz) {
         s = ensure_partial(mat->partial, mat->partial_cap, (size_t)(2 * c.num_lanes * std::min(k, 32)) + 1);
@@ -420,6 +422,7 @@ dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t 
     const Container &c = mat->c;
     if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
     if (lddy < k || lddx < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
+    if (lddx >= (1ll << 31) || lddy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
     if ((c.n > 0 && !dX) || (c.m > 0 && c.nnz > 0 && !dY)) return set_err(DTANS_EINVAL, "null vector");
     hipError_t e = launch_spmm_t(mat->view, c.dtype == kF64, k, dY, lddy, dX, lddx, alpha, beta,
                                  plan_launch(mat), st);
@@ -506,12 +509,13 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
     }
     std::vector<DevMat> views(count);
     for (int i = 0; i < count; ++i) views[i] = mats[i]->view;
-    void *p_mats, *p_tasks, *p_wg;
+    void *p_mats, *p_tasks, *p_wg, *p_ptrs;
     hipStream_t st = nullptr;
     hipError_t e;
     if ((e = b->bufs.upload(&p_mats, views.data(), sizeof(DevMat) * views.size(), st)) != hipSuccess ||
         (e = b->bufs.upload(&p_tasks, b->tasks.data(), sizeof(BatchTask) * b->tasks.size(), st)) != hipSuccess ||
         (e = b->bufs.upload(&p_wg, b->wg_task.data(), 4 * b->wg_task.size(), st)) != hipSuccess ||
+        (e = b->bufs.upload(&p_ptrs, nullptr, 2 * sizeof(void *) * (size_t)count, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         delete b;
         return hip_err(e, "dtans_batch_create upload");
@@ -519,6 +523,7 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
     b->dev.mats = (const DevMat *)p_mats;
     b->dev.tasks = (const BatchTask *)p_tasks;
     b->dev.wg_task = (const int32_t *)p_wg;
+    b->dev.ptrs = (void *const *)p_ptrs;
     b->launch.waves_per_wg = wpw;
     b->launch.grid = grid;
     *out = b;
@@ -530,14 +535,14 @@ dtans_status dtans_batch_spmv(dtans_batch *b, const void *const *xs, void *const
     if (!b || !xs || !ys) return set_err(DTANS_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
     const size_t cnt = b->mats.size();
-    BatchDev dev = b->dev;
+    BatchPtrs ptrs{};
     for (size_t i = 0; i < cnt; ++i) {
         if ((b->mats[i]->c.m > 0 && !ys[i]) || (b->mats[i]->c.nnz > 0 && !xs[i]))
             return set_err(DTANS_EINVAL, "null vector in batch");
-        dev.xs[i] = xs[i];
-        dev.ys[i] = ys[i];
+        ptrs.xs[i] = xs[i];
+        ptrs.ys[i] = ys[i];
     }
-    hipError_t e = launch_batch(dev, b->f64, alpha, beta, b->launch, st);
+    hipError_t e = launch_batch(b->dev, ptrs, (int)cnt, b->f64, alpha, beta, b->launch, st);
     if (e != hipSuccess) return hip_err(e, "dtans_batch_spmv launch");
     return DTANS_OK;
 }

@@ -55,107 +55,204 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
 }
 
 // ------------------------------------------------------------------ sinks
-// A sink consumes the decoded nonzeros of one lane in order:
-//   nz(g, row, col, v): nonzero number g (row-major), its row, column, value
-//   row_done(row, kind): the lane has seen its last nonzero of `row`; kind
+// A sink consumes one lane's decoded nonzeros a segment at a time:
+//   segment<MULTI>(col, v, nreal, g, rowk): nonzeros k < nreal with columns
+//     col[k] and values v[k]; nonzero k is number g + k in row-major order and
+//     lies in row rowk[k].  MULTI is false when a lane holds a single row.
+//     Every sink issues all its loads for the segment before it uses any.
+//   finish_row(row, kind): the lane has seen its last nonzero of `row`; kind
 //     says whether the lane holds the whole row, its head (the row started in
 //     an earlier lane) or its tail (the row continues in later lanes).
+//   empty_row(row): a row without nonzeros that this lane owns.
+// Rows that end in the middle of a lane are finished inside segment().
 
-template <typename VT, int KC>
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// y (k columns) = alpha * A x + beta * y.  UNIT: k = 1 with unit strides.
+// ACC: accumulator type.  double everywhere except FP32 SpMM with many
+// columns in the nonzero-balanced layout, where a lane sums a bounded number
+// of nonzeros (at most 1024; measured error ~1e-7 of |A||x| at 512) before
+// its partial sums are combined in double.
+template <typename VT, int KC, bool UNIT, typename ACC = double>
 struct SpmmSink {
+    static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
     struct Params {
         const VT *X;
-        int64_t ldx;
+        uint32_t ldx;
         VT *Y;
-        int64_t ldy;
+        uint32_t ldy;
         double *partial;  // [lane][head/tail][KC]
-        int64_t n;
         double alpha, beta;
     };
     const Params p;
     int64_t lane;
-    double acc[KC];
-    __device__ SpmmSink(const Params &pp, int64_t l) : p(pp), lane(l) {
+    int32_t cur, head_row;  // row being accumulated; the lane's head row or -1
+    ACC acc[KC];
+    // cur starts at -1: a row is finished only after the sink has seen one of
+    // its nonzeros (empty rows are written by the decoder via empty_row)
+    __device__ SpmmSink(const Params &pp, int64_t l, int32_t first_row, bool first_is_head)
+        : p(pp), lane(l), cur(-1), head_row(first_is_head ? first_row : -1) {
 #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+        for (int c = 0; c < KC; ++c) acc[c] = (ACC)0;
     }
-    __device__ __forceinline__ void nz(int64_t, int32_t, uint32_t col, VT v) {
-        const uint32_t cc = min(col, (uint32_t)(p.n - 1));  // memory safety only
-        const VT *x = p.X + (int64_t)cc * p.ldx;
-#pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = fma((double)v, (double)x[c], acc[c]);
+    __device__ __forceinline__ const VT *xrow(uint32_t col) const {
+        return UNIT ? p.X + col : p.X + (uint64_t)col * p.ldx;
     }
-    __device__ __forceinline__ void row_done(int32_t row, int kind) {
+    __device__ __forceinline__ void store(int32_t row, int kind) {
         if (kind == kComplete) {
-            VT *y = p.Y + (int64_t)row * p.ldy;
+            VT *y = UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy;
 #pragma unroll
             for (int c = 0; c < KC; ++c)
-                y[c] = (VT)(p.beta == 0.0 ? p.alpha * acc[c] : p.alpha * acc[c] + p.beta * (double)y[c]);
+                y[c] = (VT)(p.beta == 0.0 ? p.alpha * (double)acc[c]
+                                          : p.alpha * (double)acc[c] + p.beta * (double)y[c]);
         } else {
             double *q = p.partial + (2 * lane + (kind == kTail ? 1 : 0)) * KC;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) q[c] = acc[c];
+            for (int c = 0; c < KC; ++c) q[c] = (double)acc[c];
         }
 #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+        for (int c = 0; c < KC; ++c) acc[c] = (ACC)0;
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
+                                            int64_t, const int32_t rowk[4]) {
+        if (KC <= 4) {
+            VT x[4][KC];
+            if (nreal >= 4 && (!MULTI || rowk[3] == cur)) {  // common case: no tail, no row end
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) x[k][c] = xrow(col[k])[c];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)v[k], (ACC)x[k][c], acc[c]);
+                return;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < nreal)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) x[k][c] = xrow(col[k])[c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < nreal) {
+                    if (MULTI && rowk[k] != cur) {
+                        if (cur >= 0) store(cur, cur == head_row ? kHead : kComplete);
+                        cur = rowk[k];
+                    }
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)v[k], (ACC)x[k][c], acc[c]);
+                }
+        } else {
+            // wide rows of X: load nonzero k+1 while multiplying nonzero k
+            VT xa[KC], xb[KC];
+            if (nreal > 0) {
+#pragma unroll
+                for (int c = 0; c < KC; ++c) xa[c] = xrow(col[0])[c];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                VT *xc = (k & 1) ? xb : xa;
+                VT *xn = (k & 1) ? xa : xb;
+                if (k + 1 < 4 && k + 1 < nreal) {
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) xn[c] = xrow(col[k + 1])[c];
+                }
+                if (k < nreal) {
+                    if (MULTI && rowk[k] != cur) {
+                        if (cur >= 0) store(cur, cur == head_row ? kHead : kComplete);
+                        cur = rowk[k];
+                    }
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)v[k], (ACC)xc[c], acc[c]);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void finish_row(int32_t row, int kind) { store(row, kind); }
+    __device__ __forceinline__ void empty_row(int32_t row) {
+        VT *y = UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) y[c] = p.beta == 0.0 ? (VT)0 : (VT)(p.beta * (double)y[c]);
     }
 };
 
+// dX (k columns) += alpha * A^T dY, scattered with atomic adds.
 template <typename VT, int KC>
 struct TransSink {
+    static constexpr int kOcc = KC <= 2 ? 8 : 4;
     struct Params {
         const VT *dY;
-        int64_t lddy;
+        uint32_t lddy;
         VT *dX;
-        int64_t lddx;
-        int64_t n;
+        uint32_t lddx;
         double alpha;
     };
     const Params p;
-    int32_t cur = -1;
+    int32_t cur;
     VT dy[KC];
-    __device__ TransSink(const Params &pp, int64_t) : p(pp) {}
-    __device__ __forceinline__ void nz(int64_t, int32_t row, uint32_t col, VT v) {
-        if (row != cur) {
-            cur = row;
-            const VT *src = p.dY + (int64_t)row * p.lddy;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) dy[c] = (VT)(p.alpha * (double)src[c]);
-        }
-        const uint32_t cc = min(col, (uint32_t)(p.n - 1));
-        VT *dst = p.dX + (int64_t)cc * p.lddx;
-#pragma unroll
-        for (int c = 0; c < KC; ++c) unsafeAtomicAdd(dst + c, v * dy[c]);
+    __device__ TransSink(const Params &pp, int64_t, int32_t first_row, bool) : p(pp), cur(-1) {
+        (void)first_row;
     }
-    __device__ __forceinline__ void row_done(int32_t, int) {}
+    __device__ __forceinline__ void load_row(int32_t row) {
+        cur = row;
+        const VT *src = p.dY + (uint64_t)(uint32_t)row * p.lddy;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) dy[c] = (VT)(p.alpha * (double)src[c]);
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
+                                            int64_t, const int32_t rowk[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nreal) {
+                if (rowk[k] != cur) load_row(rowk[k]);
+                VT *dst = p.dX + (uint64_t)col[k] * p.lddx;
+#pragma unroll
+                for (int c = 0; c < KC; ++c) unsafeAtomicAdd(dst + c, v[k] * dy[c]);
+            }
+    }
+    __device__ __forceinline__ void finish_row(int32_t, int) {}
+    __device__ __forceinline__ void empty_row(int32_t) {}
 };
 
+// decode to CSR: column and value bits of every nonzero
 template <typename VT>
 struct DecodeSink {
+    static constexpr int kOcc = 8;
     struct Params {
         int32_t *col;
         typename Bits<VT>::T *vals;
     };
     const Params p;
-    __device__ DecodeSink(const Params &pp, int64_t) : p(pp) {}
-    __device__ __forceinline__ void nz(int64_t g, int32_t, uint32_t col, VT v) {
-        p.col[g] = (int32_t)col;
-        p.vals[g] = __builtin_bit_cast(typename Bits<VT>::T, v);
+    __device__ DecodeSink(const Params &pp, int64_t, int32_t, bool) : p(pp) {}
+    template <bool MULTI>
+    __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
+                                            int64_t g, const int32_t *) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nreal) {
+                p.col[g + k] = (int32_t)col[k];
+                p.vals[g + k] = __builtin_bit_cast(typename Bits<VT>::T, v[k]);
+            }
     }
-    __device__ __forceinline__ void row_done(int32_t, int) {}
+    __device__ __forceinline__ void finish_row(int32_t, int) {}
+    __device__ __forceinline__ void empty_row(int32_t) {}
 };
 
 // --------------------------------------------------------- wave decoding
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
-// nonzeros of this thread's lane to `sink`.
+// nonzeros of this thread's lane to a sink constructed here.
 template <int LAYOUT, typename VT, class Sink>
 __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
                                              const VT *__restrict__ tval, int64_t slice,
-                                             uint32_t lane, Sink &sink) {
+                                             uint32_t lane, const typename Sink::Params &sp) {
     const int64_t l = slice * kWave + lane;
     const bool live = l < a.num_lanes;
-    int64_t g0 = 0, cnt = 0;
-    int32_t row = 0, row_beg = 0, row_end = 0;
+    int64_t g0 = 0;
+    int cnt = 0;
+    int32_t row = 0, row_beg = 0, row_end = 0, next_end = 0;
     if (live) {
         if (LAYOUT == 1) {
             row = (int32_t)l;
@@ -164,29 +261,32 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             g0 = row_beg;
         } else {
             g0 = l * (int64_t)a.lane_nnz;
-            cnt = min((int64_t)a.lane_nnz, a.nnz - g0);
+            cnt = (int)min((int64_t)a.lane_nnz, a.nnz - g0);
             row = a.lane_row[l];
             row_beg = a.row_ptr[row];
             row_end = a.row_ptr[row + 1];
+            next_end = row + 2 <= a.m ? a.row_ptr[row + 2] : (int32_t)a.nnz;
         }
     }
-    const int S = (int)((cnt + 3) >> 2);
+    Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
+    const int S = (cnt + 3) >> 2;
     const int Smax = wave_max(S);
 
-    // per-wave stream bases are uniform; offsets into them stay 32-bit and
-    // uniform (popcounts of ballots), so the compiler keeps them in SGPRs
-    const uint32_t *__restrict__ W = a.words + a.woff[slice];
+    // per-wave stream bases are uniform; offsets into them are 32-bit byte
+    // offsets that stay uniform (popcounts of ballots) and live in SGPRs
+    const char *__restrict__ W = (const char *)(a.words + a.woff[slice]);
     const uint32_t *__restrict__ ED = a.escd + a.doff[slice];
     const VT *__restrict__ EV = (const VT *)a.escv + a.voff[slice];
+    auto word = [&](uint32_t byte_off) { return *(const uint32_t *)(W + byte_off); };
     uint32_t pos, dpos = 0, vpos = 0;
     uint32_t w1, w2, w3;
     {
         // lanes without a stream read a neighbouring word (buffers are padded)
-        const uint64_t mk = __ballot(S > 0);
-        const uint32_t pre = lane_prefix(mk), c = (uint32_t)__popcll(mk);
-        w1 = W[pre];
-        w2 = W[c + pre];
-        w3 = W[2 * c + pre];
+        const uint64_t mk = ballot(S > 0);
+        const uint32_t pre = 4 * lane_prefix(mk), c = 4 * (uint32_t)__popcll(mk);
+        w1 = word(pre);
+        w2 = word(c + pre);
+        w3 = word(2 * c + pre);
         pos = 3 * c;
     }
     uint32_t d = 0, r = 1, col = 0;
@@ -194,7 +294,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     for (int j = 0; j < Smax; ++j) {
         const bool act = j < S;
         const bool more = j + 1 < S;
-        const int rem = (int)cnt - 4 * j;
+        const int rem = cnt - 4 * j;
         uint32_t sl[8];
         unpack8(w1, w2, w3, sl);
         uint64_t e[8];
@@ -204,9 +304,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] = tval[sl[2 * k + 1]];
         // The next segment's words first, so that their loads are in flight
-        // while this segment's escapes and x gathers are served.  Loads are
-        // issued by every lane and the extracted word selected afterwards;
-        // lanes that do not load read a neighbouring word of the stream.
+        // while this segment's escapes and x gathers are served.  Every lane
+        // issues the loads and selects the extracted word afterwards; lanes
+        // that do not load read a neighbouring word of the stream.
         if (j + 1 < Smax) {
             uint32_t D, Rm1, x1, x2;
             group4((uint32_t)(e[0] >> 32) & 0xffffu, (uint32_t)(e[1] >> 48),
@@ -215,14 +315,14 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             group4((uint32_t)(e[4] >> 32) & 0xffffu, (uint32_t)(e[5] >> 48),
                    (uint32_t)(e[6] >> 32) & 0xffffu, (uint32_t)(e[7] >> 48), D, Rm1);
             const bool ext2 = append_and_check(d, r, D, Rm1, x2);
-            const uint64_t m1 = __ballot(more && !ext1);
-            const uint64_t m2 = __ballot(more && !ext2);
-            const uint64_t m3 = __ballot(more);
-            const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
-            const uint32_t l1 = W[pos + lane_prefix(m1)];
-            const uint32_t l2 = W[pos + c1 + lane_prefix(m2)];
-            const uint32_t l3 = W[pos + c1 + c2 + lane_prefix(m3)];
-            pos += c1 + c2 + (uint32_t)__popcll(m3);
+            const uint64_t m1 = ballot(more && !ext1);
+            const uint64_t m2 = ballot(more && !ext2);
+            const uint64_t m3 = ballot(more);
+            const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
+            const uint32_t l1 = word(pos + 4 * lane_prefix(m1));
+            const uint32_t l2 = word(pos + c1 + 4 * lane_prefix(m2));
+            const uint32_t l3 = word(pos + c1 + c2 + 4 * lane_prefix(m3));
+            pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
             w1 = ext1 ? x1 : l1;
             w2 = ext2 ? x2 : l2;
             w3 = l3;
@@ -235,59 +335,72 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         // their last segment need masking.
         const uint32_t escd_any = (uint32_t)e[0] | (uint32_t)e[2] | (uint32_t)e[4] | (uint32_t)e[6];
         const uint32_t escv_any = (uint32_t)e[1] | (uint32_t)e[3] | (uint32_t)e[5] | (uint32_t)e[7];
-        if (__ballot(act && (((escd_any >> 1) | escv_any) & (1u << 30)))) {  // wave-uniform
+        if (ballot(act && (((escd_any >> 1) | escv_any) & (1u << 30)))) {  // wave-uniform
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const bool f = act && k < rem && ((uint32_t)e[2 * k] >> 31);
-                const uint64_t mk = __ballot(f);
+                const uint64_t mk = ballot(f);
                 if (f) dl[k] = ED[dpos + lane_prefix(mk)];
                 dpos += (uint32_t)__popcll(mk);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const bool f = act && k < rem && (((uint32_t)e[2 * k + 1] >> 30) & 1u);
-                const uint64_t mk = __ballot(f);
+                const uint64_t mk = ballot(f);
                 if (f) v[k] = EV[vpos + lane_prefix(mk)];
                 vpos += (uint32_t)__popcll(mk);
             }
         }
+        const int nreal = act ? min(rem, 4) : 0;
+        uint32_t cols[4];
+        int32_t rowk[4];
         if (LAYOUT == 1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 col += dl[k];
-                if (act && k < rem) sink.nz(g + k, row, col, v[k]);
+                cols[k] = col;
+                rowk[k] = row;
             }
-            g += 4;
+            sink.template segment<false>(cols, v, nreal, g, rowk);
         } else {
+            // resolve row boundaries first: a column delta restarts at every
+            // row; empty rows passed over are written here, rows with
+            // nonzeros are finished by the sink when their successor starts
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (act && k < rem) {
-                    while (g >= row_end) {  // rows ending before this nonzero
-                        sink.row_done(row, row_beg < g0 ? kHead : kComplete);
-                        col = 0;
+                if (k < nreal) {
+                    while (g + k >= row_end) {
+                        if (row_beg == row_end) sink.empty_row(row);
                         ++row;
                         row_beg = row_end;
-                        row_end = a.row_ptr[row + 1];
+                        row_end = next_end;
+                        next_end = row + 2 <= a.m ? a.row_ptr[row + 2] : (int32_t)a.nnz;
+                        col = 0;
                     }
-                    col += dl[k];
-                    sink.nz(g, row, col, v[k]);
-                    ++g;
                 }
+                col += dl[k];
+                cols[k] = col;
+                rowk[k] = row;
             }
+            sink.template segment<true>(cols, v, nreal, g, rowk);
         }
+        g += 4;
     }
     if (!live) return;
     if (LAYOUT == 1) {
-        if (l < a.m) sink.row_done(row, kComplete);
+        if (l < a.m) sink.finish_row(row, kComplete);
     } else {
         const int64_t gend = g0 + cnt;
+        bool first = true;  // `row` holds this lane's last nonzeros
         while (row < a.m && row_end <= gend) {  // rows finished here, incl. empty ones
-            sink.row_done(row, row_beg < g0 ? kHead : kComplete);
+            if (first) sink.finish_row(row, row_beg < g0 ? kHead : kComplete);
+            else sink.empty_row(row);
+            first = false;
             ++row;
             row_beg = row_end;
             if (row < a.m) row_end = a.row_ptr[row + 1];
         }
-        if (row < a.m && row_beg < gend) sink.row_done(row, row_beg < g0 ? kHead : kTail);
+        if (first && row < a.m) sink.finish_row(row, row_beg < g0 ? kHead : kTail);
     }
 }
 
@@ -315,10 +428,7 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * wpb +
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t s0 = gw * a.num_waves / total, s1 = (gw + 1) * a.num_waves / total;
-    for (int64_t s = s0; s < s1; ++s) {
-        Sink sink(sp, s * kWave + lane);
-        decode_slice<LAYOUT, VT>(a, s_tab, s_val, s, lane, sink);
-    }
+    for (int64_t s = s0; s < s1; ++s) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
 }
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
@@ -357,7 +467,7 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
     int cur = -1;
     for (int t = t0; t < t1; ++t) {
         const BatchTask task = b.tasks[t];
-        const DevMat &a = b.mats[task.mat];
+        const DevMat a = b.mats[task.mat];  // uniform: scalar loads into SGPRs
         if (task.mat != cur) {  // restage the tables only when the matrix changes
             __syncthreads();
             const VT *tv = (const VT *)a.tabval;
@@ -368,20 +478,16 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
             __syncthreads();
             cur = task.mat;
         }
-        typename SpmmSink<VT, 1>::Params sp;
-        sp.X = (const VT *)b.xs[task.mat];
+        typename SpmmSink<VT, 1, true>::Params sp;
+        sp.X = (const VT *)b.ptrs[2 * task.mat];
         sp.ldx = 1;
-        sp.Y = (VT *)b.ys[task.mat];
+        sp.Y = (VT *)b.ptrs[2 * task.mat + 1];
         sp.ldy = 1;
         sp.partial = nullptr;
-        sp.n = a.n;
         sp.alpha = alpha;
         sp.beta = beta;
-        for (int w = wib; w < task.num_waves; w += wpb) {
-            const int64_t s = task.first_wave + w;
-            SpmmSink<VT, 1> sink(sp, s * kWave + lane);
-            decode_slice<1, VT>(a, s_tab, s_val, s, lane, sink);
-        }
+        for (int w = wib; w < task.num_waves; w += wpb)
+            decode_slice<1, VT, SpmmSink<VT, 1, true>>(a, s_tab, s_val, task.first_wave + w, lane, sp);
     }
 }
 
@@ -474,12 +580,23 @@ __global__ __launch_bounds__(256) void csr_split_kernel(CsrDev c, const VT *__re
 }
 
 // ------------------------------------------------------------ dispatch
+template <class T> struct TypeBox { typedef T type; };
+
+// the nonzero-balanced layout tracks rows and needs a few more registers
+constexpr int occ_nnz(int occ) { return occ > 7 ? 7 : occ; }
+
+template <typename F>
+hipError_t for_kc(int k, int kcmax, F f);
 template <typename F>
 hipError_t for_kc(int k, F f) {
-    // split k columns into compile-time chunks
+    return for_kc(k, 32, f);
+}
+template <typename F>
+hipError_t for_kc(int k, int kcmax, F f) {
+    // split k columns into compile-time chunks of at most kcmax
     int c0 = 0;
     while (c0 < k) {
-        int left = k - c0;
+        int left = k - c0 < kcmax ? k - c0 : kcmax;
         hipError_t e;
         if (left >= 32) { e = f(std::integral_constant<int, 32>(), c0); c0 += 32; }
         else if (left >= 16) { e = f(std::integral_constant<int, 16>(), c0); c0 += 16; }
@@ -506,23 +623,22 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
             return hipGetLastError();
         });
     }
-    return for_kc(k, [&](auto KCc, int c0) {
-        constexpr int KC = decltype(KCc)::value;
-        typename SpmmSink<VT, KC>::Params sp;
+    auto launch = [&](auto sinkc, int KC, int c0) -> hipError_t {
+        typedef typename decltype(sinkc)::type SinkT;
+        typename SinkT::Params sp;
         sp.X = X + c0;
-        sp.ldx = ldx;
+        sp.ldx = (uint32_t)ldx;
         sp.Y = Y + c0;
-        sp.ldy = ldy;
+        sp.ldy = (uint32_t)ldy;
         sp.partial = partial;
-        sp.n = a.n;
         sp.alpha = alpha;
         sp.beta = beta;
         if (a.layout == 1)
-            hipLaunchKernelGGL((decode_kernel<1, VT, SpmmSink<VT, KC>, (KC <= 2 ? 7 : 4)>), dim3(L.grid), block, 0, st,
-                               a, sp);
+            hipLaunchKernelGGL((decode_kernel<1, VT, SinkT, SinkT::kOcc>), dim3(L.grid), block, 0,
+                               st, a, sp);
         else
-            hipLaunchKernelGGL((decode_kernel<2, VT, SpmmSink<VT, KC>, (KC <= 2 ? 7 : 4)>), dim3(L.grid), block, 0, st,
-                               a, sp);
+            hipLaunchKernelGGL((decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc)>), dim3(L.grid),
+                               block, 0, st, a, sp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (a.layout == 2 && a.nsplit > 0) {
@@ -533,6 +649,21 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
             e = hipGetLastError();
         }
         return e;
+    };
+    if (k == 1 && ldx == 1 && ldy == 1) return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
+    // widest column chunk that fits the registers without spilling
+    const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
+    const int kcmax = std::is_same<VT, double>::value ? 8 : 16;
+    return for_kc(k, kcmax, [&](auto KCc, int c0) {
+        constexpr int KC = decltype(KCc)::value;
+        if constexpr (std::is_same<VT, float>::value && KC >= 8 && KC <= 16) {
+            if (f32acc) return launch(TypeBox<SpmmSink<VT, KC, false, float>>(), KC, c0);
+        }
+        if constexpr (KC > 16 || (std::is_same<VT, double>::value && KC > 8)) {
+            return hipErrorInvalidValue;  // excluded by kcmax
+        } else {
+            return launch(TypeBox<SpmmSink<VT, KC, false>>(), KC, c0);
+        }
     });
 }
 
@@ -549,17 +680,16 @@ hipError_t spmm_t_impl(const DevMat &a, int k, const VT *dY, int64_t lddy, VT *d
         if (e != hipSuccess || a.nnz == 0 || a.num_waves == 0) return e;
         typename TransSink<VT, KC>::Params sp;
         sp.dY = dY + c0;
-        sp.lddy = lddy;
+        sp.lddy = (uint32_t)lddy;
         sp.dX = dX + c0;
-        sp.lddx = lddx;
-        sp.n = a.n;
+        sp.lddx = (uint32_t)lddx;
         sp.alpha = alpha;
         const dim3 block(64 * L.waves_per_wg);
         if (a.layout == 1)
-            hipLaunchKernelGGL((decode_kernel<1, VT, TransSink<VT, KC>, (KC <= 2 ? 7 : 4)>), dim3(L.grid), block, 0,
+            hipLaunchKernelGGL((decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc>), dim3(L.grid), block, 0,
                                st, a, sp);
         else
-            hipLaunchKernelGGL((decode_kernel<2, VT, TransSink<VT, KC>, (KC <= 2 ? 7 : 4)>), dim3(L.grid), block, 0,
+            hipLaunchKernelGGL((decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc)>), dim3(L.grid), block, 0,
                                st, a, sp);
         return hipGetLastError();
     });
@@ -573,9 +703,9 @@ hipError_t decode_impl(const DevMat &a, int32_t *col, void *vals, Launch L, hipS
     sp.vals = (typename Bits<VT>::T *)vals;
     const dim3 block(64 * L.waves_per_wg);
     if (a.layout == 1)
-        hipLaunchKernelGGL((decode_kernel<1, VT, DecodeSink<VT>, 7>), dim3(L.grid), block, 0, st, a, sp);
+        hipLaunchKernelGGL((decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc>), dim3(L.grid), block, 0, st, a, sp);
     else
-        hipLaunchKernelGGL((decode_kernel<2, VT, DecodeSink<VT>, 7>), dim3(L.grid), block, 0, st, a, sp);
+        hipLaunchKernelGGL((decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc)>), dim3(L.grid), block, 0, st, a, sp);
     return hipGetLastError();
 }
 
@@ -652,8 +782,22 @@ hipError_t launch_decode(const DevMat &a, bool f64, int32_t *col, void *vals, La
     return f64 ? decode_impl<double>(a, col, vals, L, st) : decode_impl<float>(a, col, vals, L, st);
 }
 
-hipError_t launch_batch(const BatchDev &b, bool f64, double alpha, double beta, Launch L,
-                        hipStream_t st) {
+// copies the x / y pointers of one call from the launch arguments into the
+// batch's device pointer table (stream-ordered with the batch kernel)
+__global__ void batch_ptrs_kernel(BatchPtrs p, int count, void **table) {
+    const int i = threadIdx.x;
+    if (i < count) {
+        table[2 * i] = (void *)p.xs[i];
+        table[2 * i + 1] = p.ys[i];
+    }
+}
+
+hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, bool f64, double alpha,
+                        double beta, Launch L, hipStream_t st) {
+    hipLaunchKernelGGL(batch_ptrs_kernel, dim3(1), dim3(kMaxBatch), 0, st, ptrs, count,
+                       (void **)b.ptrs);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     const dim3 block(64 * L.waves_per_wg);
     if (f64)
         hipLaunchKernelGGL(batch_kernel<double>, dim3(L.grid), block, 0, st, b, alpha, beta);

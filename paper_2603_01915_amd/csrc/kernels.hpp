@@ -50,12 +50,17 @@ struct BatchDev {
     const DevMat *mats;      // device array of matrix views
     const BatchTask *tasks;  // device array, grouped per workgroup
     const int32_t *wg_task;  // device, grid + 1 offsets into tasks
-    // x / y device pointers of each matrix, passed by value with the launch
+    void *const *ptrs;       // device table: x, y pointer of each matrix
+};
+// x / y device pointers of one call, passed by value with a launch
+struct BatchPtrs {
     const void *xs[kMaxBatch];
     void *ys[kMaxBatch];
 };
-hipError_t launch_batch(const BatchDev &b, bool f64, double alpha, double beta, Launch L,
-                        hipStream_t st);
+// Rewrites the pointer table on `st` and launches; calls on one batch must
+// stay on one stream (the table is shared by its launches).
+hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, bool f64, double alpha,
+                        double beta, Launch L, hipStream_t st);
 
 // plain CSR baseline.  variant 1: G lanes per row; variant 2: lane_nnz
 // nonzeros per lane with partials + fix-up (lane_row, split_* as for DevMat).
