@@ -175,8 +175,10 @@ void dtans_batch_destroy(dtans_batch *batch);
  * Plain CSR baseline on the same GPU (the uncompressed comparison format of
  * Sec. V).  dtans_csr_create copies host CSR arrays (row_ptr m+1, col_idx
  * nnz, vals nnz) to the current device and plans the launch; variant:
- * 0 = automatic, 1 = a group of lanes per row sized by the mean row length,
- * 2 = equal nonzeros per lane with a fix-up for rows that cross lanes.
+ * 0 = automatic (3), 1 = a group of lanes per row sized by the mean row
+ * length, 2 = equal nonzeros per lane with a fix-up for rows that cross lanes,
+ * 3 = CSR-stream: row blocks of at most 1024 nonzeros staged through LDS
+ * (single-vector products; several right-hand sides use variant 1).
  * dtans_csr_spmv / dtans_csr_spmm compute y = alpha*A*x + beta*y and
  * Y = alpha*A*X + beta*Y with the same conventions as dtans_spmv / _spmm.
  */

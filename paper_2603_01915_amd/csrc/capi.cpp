@@ -568,8 +568,8 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
     for (int64_t q = 0; q < nnz; ++q)
         if (col_idx[q] < 0 || col_idx[q] >= n) return set_err(DTANS_ERANGE, "column index out of range");
     const double mean = m ? (double)nnz / m : 0.0;
-    if (variant == 0) variant = (maxlen > 16 * std::max(mean, 4.0)) ? 2 : 1;
-    if (variant != 1 && variant != 2) return set_err(DTANS_EINVAL, "variant must be 0, 1 or 2");
+    if (variant == 0) variant = 3;
+    if (variant < 1 || variant > 3) return set_err(DTANS_EINVAL, "variant must be 0, 1, 2 or 3");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     dtans_csr *h = new dtans_csr();
@@ -602,10 +602,28 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         c.num_lanes = tmp.num_lanes;
         c.nsplit = (int64_t)split_row.size();
     }
-    void *p[7];
+    std::vector<int32_t> blk;  // CSR-stream row blocks: <= 1024 nonzeros or one long row
+    if (variant == 3) {
+        const int64_t cap = 1024, max_rows = 4096;
+        blk.push_back(0);
+        int64_t r = 0;
+        while (r < m) {
+            int64_t e = r, cnt = 0;
+            while (e < m && e - r < max_rows && cnt + (row_ptr[e + 1] - row_ptr[e]) <= cap) {
+                cnt += row_ptr[e + 1] - row_ptr[e];
+                ++e;
+            }
+            if (e == r) e = r + 1;  // a row longer than the block: its own block
+            blk.push_back((int32_t)e);
+            r = e;
+        }
+        c.nblk = (int64_t)blk.size() - 1;
+    }
+    void *p[8];
     hipStream_t st = nullptr;
     hipError_t e;
-    if ((e = h->bufs.upload(&p[0], row_ptr, 4 * (size_t)(m + 1), st)) != hipSuccess ||
+    if ((e = h->bufs.upload(&p[7], blk.data(), 4 * blk.size(), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[0], row_ptr, 4 * (size_t)(m + 1), st)) != hipSuccess ||
         (e = h->bufs.upload(&p[1], col_idx, 4 * (size_t)nnz, st)) != hipSuccess ||
         (e = h->bufs.upload(&p[2], vals, vb * (size_t)nnz, st)) != hipSuccess ||
         (e = h->bufs.upload(&p[3], lane_row.data(), 4 * lane_row.size(), st)) != hipSuccess ||
@@ -623,8 +641,10 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
     c.split_row = (const int32_t *)p[4];
     c.split_first = (const int32_t *)p[5];
     c.split_last = (const int32_t *)p[6];
+    c.blk = (const int32_t *)p[7];
     h->bytes = 4 * (m + 1) + nnz * (4 + (int64_t)vb) +
-               (variant == 2 ? 4 * c.num_lanes + 12 * c.nsplit : 0);
+               (variant == 2 ? 4 * c.num_lanes + 12 * c.nsplit : 0) +
+               (variant == 3 ? 4 * (c.nblk + 1) : 0);
     *out = h;
     return DTANS_OK;
 }

@@ -579,6 +579,70 @@ __global__ __launch_bounds__(256) void csr_split_kernel(CsrDev c, const VT *__re
     if (row < c.m && row_beg < gend) done(row_beg < g0 ? kHead : kTail);
 }
 
+// variant 3 (SpMV): CSR-stream.  A workgroup takes a block of consecutive
+// rows holding at most kStreamNnz nonzeros, loads their column indices and
+// values coalesced (four per thread, all x gathers in flight together),
+// stages the products in LDS and sums each row from LDS.  A block that is a
+// single row longer than that is reduced across the workgroup instead.
+constexpr int kStreamNnz = 1024;
+template <typename VT>
+__global__ __launch_bounds__(256) void csr_stream_kernel(CsrDev c, const int32_t *__restrict__ blk,
+                                                         const VT *__restrict__ x, VT *__restrict__ y,
+                                                         double alpha, double beta) {
+    __shared__ double prod[kStreamNnz];
+    __shared__ double red[4];
+    const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+    const int32_t g0 = c.row_ptr[r0], g1 = c.row_ptr[r1];
+    const VT *__restrict__ val = (const VT *)c.val;
+    const int32_t *__restrict__ col = c.col;
+    const int tid = threadIdx.x;
+    if (g1 - g0 > kStreamNnz) {  // one long row
+        double s = 0.0;
+        for (int32_t base = g0; base < g1; base += 4 * 256) {
+            VT v[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t i = base + u * 256 + tid;
+                v[u] = i < g1 ? val[i] : (VT)0;
+                xv[u] = i < g1 ? x[col[i]] : (VT)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s = fma((double)v[u], (double)xv[u], s);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((tid & 63) == 0) red[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0) {
+            const double t = red[0] + red[1] + red[2] + red[3];
+            y[r0] = (VT)(beta == 0.0 ? alpha * t : alpha * t + beta * (double)y[r0]);
+        }
+        return;
+    }
+    const int32_t cnt = g1 - g0;
+    VT v[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int32_t i = u * 256 + tid;
+        if (i < cnt) {
+            v[u] = val[g0 + i];
+            xv[u] = x[col[g0 + i]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int32_t i = u * 256 + tid;
+        if (i < cnt) prod[i] = (double)v[u] * (double)xv[u];
+    }
+    __syncthreads();
+    for (int r = r0 + tid; r < r1; r += 256) {
+        const int32_t b = c.row_ptr[r] - g0, e = c.row_ptr[r + 1] - g0;
+        double s = 0.0;
+        for (int32_t i = b; i < e; ++i) s += prod[i];
+        y[r] = (VT)(beta == 0.0 ? alpha * s : alpha * s + beta * (double)y[r]);
+    }
+}
+
 // ------------------------------------------------------------ dispatch
 template <class T> struct TypeBox { typedef T type; };
 
@@ -719,6 +783,11 @@ hipError_t csr_impl(const CsrDev &c, int k, const VT *X, int64_t ldx, VT *Y, int
             const int64_t tot = c.m * KC;
             hipLaunchKernelGGL(scale_kernel<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                                st, Y + c0, c.m, KC, ldy, beta);
+            return hipGetLastError();
+        }
+        if (c.variant == 3 && KC == 1 && ldx == 1 && ldy == 1) {
+            hipLaunchKernelGGL(csr_stream_kernel<VT>, dim3((unsigned)c.nblk), dim3(256), 0, st, c,
+                               c.blk, X + c0, Y + c0, alpha, beta);
             return hipGetLastError();
         }
         if (c.variant == 2) {

@@ -64,11 +64,14 @@ hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, boo
 
 // plain CSR baseline.  variant 1: G lanes per row; variant 2: lane_nnz
 // nonzeros per lane with partials + fix-up (lane_row, split_* as for DevMat).
+// variant 3: CSR-stream row blocks (blk: first row of each block, nblk + 1
+// entries) for single-vector products; other k fall back to variant 1.
 struct CsrDev {
     const int32_t *row_ptr, *col;
     const void *val;
     const int32_t *lane_row, *split_row, *split_first, *split_last;
-    int64_t m, n, nnz, num_lanes, nsplit;
+    const int32_t *blk;
+    int64_t m, n, nnz, num_lanes, nsplit, nblk;
     int32_t variant, group, lane_nnz;
 };
 hipError_t launch_csr(const CsrDev &c, bool f64, int k, const void *X, int64_t ldx, void *Y,

@@ -171,7 +171,7 @@ def test_spmm_t_parity(layout, T, dtype, k):
             assert rel_error(out[:, c], ref, scale) <= TOL[dtype], (name, c)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_csr_baseline_parity(variant, dtype):
     torch = need_gpu()
