@@ -59,6 +59,36 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "dtans_core.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2603_01915_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, info):
+    """HBM bytes per launch of the decode kernel from the committed counter
+    summary (profiles/<workload>_traffic.txt), if it was taken on the current
+    kernel sources and the same encoded size; else None."""
+    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if int(kv.get("dtans_total_bytes", -1)) != info["total_bytes"]:
+        return None
+    return int(kv["hbm_bytes_per_launch"])
+
+
 def time_steps(torch, fn, steps, warmup):
     for i in range(warmup):
         fn(i)
@@ -116,7 +146,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
-    ap.add_argument("--traffic", default=None, help="JSON with measured HBM bytes per launch")
+    ap.add_argument("--no-warm", action="store_true", help="skip the single-copy (warm) timing")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,6 +163,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a kernel that reads and writes exactly MIB MiB each: the HBM byte
+        # counters of a profiled run are scaled by what they report for it
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     log("generating workload %s" % args.workload)
     W = make_workload(args.workload)
     rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
@@ -177,7 +218,7 @@ def main():
 
     log("timing %d steps over %d copies" % (args.steps, copies))
     ms, wall = time_steps(torch, step, args.steps, args.warmup)
-    warm_ms, _ = time_steps(torch, lambda i: step(0), args.steps, args.warmup)
+    warm_ms = None if args.no_warm else time_steps(torch, lambda i: step(0), args.steps, args.warmup)[0]
     flops = 2.0 * nnz * k
     alg_bytes = info["total_bytes"] + vec_bytes
     gflops = flops / (ms * 1e-3) / 1e9
@@ -201,13 +242,12 @@ def main():
                         "ratio_vs_smallest": round(min(info["csr_bytes"], info["coo_bytes"],
                                                        info["sell_bytes"]) / info["total_bytes"], 3),
                         "escaped_deltas": info["esc_delta"], "escaped_values": info["esc_value"]},
-        "warm": {"ms": round(warm_ms, 6), "GFLOP/s": round(flops / (warm_ms * 1e-3) / 1e9, 3),
-                 "GB/s": round(alg_bytes / (warm_ms * 1e-3) / 1e9, 2)},
+        "warm": None if warm_ms is None else {
+            "ms": round(warm_ms, 6), "GFLOP/s": round(flops / (warm_ms * 1e-3) / 1e9, 3),
+            "GB/s": round(alg_bytes / (warm_ms * 1e-3) / 1e9, 2)},
         "encode_seconds": round(enc_s, 2),
     }
-    if args.traffic:
-        with open(args.traffic) as f:
-            res["roofline"]["traffic"] = json.load(f).get("bytes_per_launch")
+    res["roofline"]["traffic"] = measured_traffic(args.workload, info)
     if not args.no_csr:
         log("plain CSR baseline")
         B = P.CsrBaseline(rp, ci, v, n)

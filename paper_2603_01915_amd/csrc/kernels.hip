@@ -38,13 +38,6 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// workgroup index renumbered so that consecutive numbers share an XCD
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
-    const int64_t x = b % kNumXcd, p = b / kNumXcd;
-    const int64_t q = G / kNumXcd, r = G % kNumXcd;
-    return x * q + (x < r ? x : r) + p;
-}
-
 template <typename VT> struct Bits;
 template <> struct Bits<double> { typedef uint64_t T; };
 template <> struct Bits<float> { typedef uint32_t T; };
@@ -424,11 +417,20 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t total = (int64_t)gridDim.x * wpb;
-    // the wave index is uniform; readfirstlane lets the compiler know it
-    const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * wpb +
-                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t s0 = gw * a.num_waves / total, s1 = (gw + 1) * a.num_waves / total;
-    for (int64_t s = s0; s < s1; ++s) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
+    // Workgroups are dispatched round-robin over the XCDs.  The workgroups of
+    // one XCD own one contiguous share of the encoded waves, and their
+    // wavefronts sweep it together (wavefront i takes waves i, i + W, ...), so
+    // at any time an XCD decodes a compact window of rows and its x gathers
+    // stay in that XCD's L2.  The wave index is uniform (readfirstlane).
+    const int64_t G = gridDim.x, xcd = blockIdx.x % kNumXcd, pos_in_xcd = blockIdx.x / kNumXcd;
+    const int64_t q = G / kNumXcd, rr = G % kNumXcd;
+    const int64_t xcd_blocks = q + (xcd < rr ? 1 : 0);
+    const int64_t xcd_first = xcd * q + (xcd < rr ? xcd : rr);
+    const int64_t s_begin = xcd_first * wpb * a.num_waves / total;
+    const int64_t s_end = (xcd_first + xcd_blocks) * wpb * a.num_waves / total;
+    const int64_t stride = xcd_blocks * wpb;
+    const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    for (int64_t s = s0; s < s_end; s += stride) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
 }
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
