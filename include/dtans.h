@@ -195,15 +195,38 @@ int64_t dtans_csr_bytes(const dtans_csr *csr);
 void dtans_csr_destroy(dtans_csr *csr);
 
 /*
- * Autotuner: encodes the CSR matrix with candidate layouts, lane lengths and
- * launch shapes, times each on the current device with k right-hand sides
- * (k = 1: SpMV), and writes the fastest options to *inout (only the fields
- * left at 0 / AUTO are searched).  budget_s bounds the wall time spent.
- * *best_ms receives the best time per multiplication.  Needs a GPU.
+ * Autotuner (encode-time parameters; no equivalent in the paper, which uses
+ * one fixed launch per GPU).  Candidate options are the fields of *in left at
+ * 0 / AUTO, searched over: layout {ROW, NNZ}; for NNZ, nonzeros per lane
+ * around the automatic choice (multiples of 4 between 32 and 512); and launch
+ * shapes (workgroups per CU up to the LDS limit, waves per workgroup filling
+ * the CU's wave slots, then half and a quarter of that).  Fields set in *in
+ * are kept in every candidate.
+ *
+ * dtans_autotune_candidates is host-only: it writes at most `cap` candidates,
+ * in the order the autotuner times them (the automatic choice first), to out
+ * (host array, may be NULL when cap == 0) and returns how many there are, or
+ * -1 on a bad argument (message in dtans_last_error).  Encoding candidates
+ * are grouped: all launch shapes of one encoding follow each other.
+ *
+ * dtans_autotune encodes each candidate encoding, uploads it to the current
+ * device and times y = A*x (k = 1) or Y = A*X (X n x k, ldx = k) with HIP
+ * events, reading a 512 MiB buffer before every timed launch so that the
+ * matrix is not served from the last-level cache.  It stops starting new
+ * encodings once budget_s seconds of wall time are spent (the first is always
+ * finished), writes the fastest options to *inout and the best time per
+ * multiplication to *best_ms.  cache_path (may be NULL) names a text file of
+ * earlier results, one line per (matrix fingerprint, dtype, k, fixed options,
+ * device name): a hit returns the stored options without encoding; a new
+ * result is appended.  Needs a GPU; blocks until its work is done.
  */
+int32_t dtans_autotune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr,
+                                  dtans_dtype dtype, int32_t k, const dtans_encode_opts *in,
+                                  dtans_encode_opts *out, int32_t cap);
 dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                             const int32_t *col_idx, const void *vals, dtans_dtype dtype, int32_t k,
-                            double budget_s, dtans_encode_opts *inout, double *best_ms);
+                            double budget_s, const char *cache_path, dtans_encode_opts *inout,
+                            double *best_ms);
 
 /* Release a handle and its device memory (NULL is ignored). */
 void dtans_destroy(dtans_matrix *mat);

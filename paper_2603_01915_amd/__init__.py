@@ -14,6 +14,7 @@ kernels need one, and everything fails loudly if ``libdtans.so`` is missing.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -21,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import DtansError, EncodeOpts, Info, LAYOUT_AUTO, LAYOUT_NNZ, LAYOUT_ROW
 
-__all__ = ["Matrix", "CsrBaseline", "Batch", "DtansError", "autotune", "version",
+__all__ = ["Matrix", "CsrBaseline", "Batch", "DtansError", "autotune", "autotune_candidates", "version",
            "LAYOUT_AUTO", "LAYOUT_ROW", "LAYOUT_NNZ"]
 
 _LAYOUTS = {"auto": LAYOUT_AUTO, "row": LAYOUT_ROW, "nnz": LAYOUT_NNZ,
@@ -325,23 +326,54 @@ class Batch:
             pass
 
 
-def autotune(row_ptr, col, vals, n: int, k: int = 1, budget_s: float = 20.0,
-             layout="auto", lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0):
-    """Search layout, nonzeros per lane and launch shape on the current GPU.
-    Returns (options dict, best milliseconds per multiplication)."""
-    L = _lib.load()
-    rp = _np(row_ptr, np.int32)
-    ci = _np(col, np.int32)
-    v = _np(vals)
+def _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows=False, perm_seed=1):
     o = EncodeOpts()
-    L.dtans_default_opts(ctypes.byref(o))
+    _lib.load().dtans_default_opts(ctypes.byref(o))
     o.layout = _LAYOUTS[layout]
     o.lane_nnz = lane_nnz
     o.waves_per_wg = waves_per_wg
     o.wg_per_cu = wg_per_cu
+    o.sort_rows = int(bool(sort_rows))
+    o.perm_seed = perm_seed
+    return o
+
+
+def _opts_dict(o) -> dict:
+    return {"layout": o.layout, "lane_nnz": o.lane_nnz, "waves_per_wg": o.waves_per_wg,
+            "wg_per_cu": o.wg_per_cu}
+
+
+def autotune_candidates(row_ptr, nnz: int, dtype=np.float64, k: int = 1, layout="auto",
+                        lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0):
+    """The options ``autotune`` would time, in its order (host only)."""
+    L = _lib.load()
+    rp = _np(row_ptr, np.int32)
+    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu)
+    code = _lib.F64 if np.dtype(dtype) == np.float64 else _lib.F32
+    cnt = L.dtans_autotune_candidates(len(rp) - 1, nnz, _ptr(rp), code, k, ctypes.byref(o), None, 0)
+    if cnt < 0:
+        raise DtansError(_lib.EINVAL, L.dtans_last_error().decode())
+    out = (EncodeOpts * max(cnt, 1))()
+    L.dtans_autotune_candidates(len(rp) - 1, nnz, _ptr(rp), code, k, ctypes.byref(o), out, cnt)
+    return [_opts_dict(out[i]) for i in range(cnt)]
+
+
+def autotune(row_ptr, col, vals, n: int, k: int = 1, budget_s: float = 20.0,
+             layout="auto", lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0,
+             cache: str | None = None):
+    """Search layout, nonzeros per lane and launch shape on the current GPU.
+    Returns (options dict for ``Matrix.from_csr``, best milliseconds per
+    multiplication).  ``cache``: optional text file of earlier results."""
+    L = _lib.load()
+    rp = _np(row_ptr, np.int32)
+    ci = _np(col, np.int32)
+    v = _np(vals)
+    if v.dtype not in (np.float32, np.float64):
+        v = v.astype(np.float64)
+    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu)
     best = ctypes.c_double()
     _lib.check(L.dtans_autotune(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
-                                _dtype_code(v), k, budget_s, ctypes.byref(o), ctypes.byref(best)))
-    opts = {"layout": o.layout, "lane_nnz": o.lane_nnz, "waves_per_wg": o.waves_per_wg,
-            "wg_per_cu": o.wg_per_cu}
-    return opts, best.value
+                                _dtype_code(v), k, budget_s,
+                                None if cache is None else os.fsencode(cache),
+                                ctypes.byref(o), ctypes.byref(best)))
+    return _opts_dict(o), best.value

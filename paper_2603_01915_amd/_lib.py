@@ -78,8 +78,12 @@ SIGNATURES = {
     "dtans_csr_spmm": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
     "dtans_csr_bytes": (_I64, [_P]),
     "dtans_csr_destroy": (None, [_P]),
+    "dtans_autotune_candidates": (_I32, [_I64, _I64, _P, ctypes.c_int, _I32,
+                                         ctypes.POINTER(EncodeOpts), ctypes.POINTER(EncodeOpts),
+                                         _I32]),
     "dtans_autotune": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, _I32, _D,
-                              ctypes.POINTER(EncodeOpts), ctypes.POINTER(ctypes.c_double)]),
+                              ctypes.c_char_p, ctypes.POINTER(EncodeOpts),
+                              ctypes.POINTER(ctypes.c_double)]),
     "dtans_destroy": (None, [_P]),
 }
 

@@ -1,6 +1,7 @@
 // C ABI of libdtans (declared in include/dtans.h).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -229,6 +230,150 @@ int64_t sell_bytes(const Container &c, int slice) {
     return total;
 }
 
+// Resolve layout AUTO and lane_nnz 0 the way dtans_encode_csr does.  One row
+// per lane unless the rows are long or irregular enough that 64-row waves
+// would be too few or badly balanced; for the nonzero layout enough lanes for
+// ~8 waves per SIMD of a 256-CU device, 32..512 nonzeros each.
+void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_encode_opts &o,
+                   int &layout, int &T) {
+    layout = o.layout;
+    if (layout == DTANS_LAYOUT_AUTO) {
+        int64_t maxlen = 0;
+        for (int64_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
+        double mean = m ? (double)nnz / m : 0;
+        int64_t waves = (m + 63) / 64;
+        layout = (waves < 2048 || maxlen > 8 * std::max(mean, 4.0)) ? DTANS_LAYOUT_NNZ : DTANS_LAYOUT_ROW;
+    }
+    T = 0;
+    if (layout == DTANS_LAYOUT_NNZ) {
+        T = o.lane_nnz;
+        if (T == 0) {
+            int64_t lanes_target = 256LL * 4 * 8 * 64;
+            int64_t t = nnz / std::max<int64_t>(1, lanes_target);
+            T = (int)std::min<int64_t>(512, std::max<int64_t>(32, (t + 3) / 4 * 4));
+        }
+    }
+}
+
+// Launch shapes for one encoding: workgroups per CU from the LDS limit down to
+// 1, waves per workgroup filling the CU's wave slots, then half and a quarter.
+std::vector<std::pair<int, int>> launch_shapes(int layout, bool f64, int wpw_fixed, int wg_fixed) {
+    const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
+    const int maxwg = std::max(1, 160 * 1024 / table_bytes);
+    const int slots = layout == DTANS_LAYOUT_ROW ? 32 : 28;
+    std::vector<std::pair<int, int>> out;  // (waves_per_wg, wg_per_cu)
+    std::vector<int> wgs;
+    if (wg_fixed) wgs.push_back(wg_fixed);
+    else
+        for (int g = maxwg; g >= 1; --g) wgs.push_back(g);
+    for (int g : wgs) {
+        const int base = std::min(16, std::max(1, slots / g));
+        std::vector<int> ws;
+        if (wpw_fixed) ws.push_back(wpw_fixed);
+        else
+            for (int w : {base, base / 2, base / 4})
+                if (w >= 2 && std::find(ws.begin(), ws.end(), w) == ws.end()) ws.push_back(w);
+        for (int w : ws) out.push_back({w, g});
+    }
+    return out;
+}
+
+dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dtans_dtype dtype,
+                             int32_t k, const dtans_encode_opts *in,
+                             std::vector<dtans_encode_opts> &out) {
+    out.clear();
+    if (!in || !row_ptr) return set_err(DTANS_EINVAL, "null argument");
+    if (m < 0 || nnz < 0) return set_err(DTANS_EINVAL, "negative size");
+    if (m >= (1ll << 31) || nnz >= (1ll << 31))
+        return set_err(DTANS_ERANGE, "rows and nonzeros must be below 2^31");
+    if (dtype != DTANS_F32 && dtype != DTANS_F64) return set_err(DTANS_EINVAL, "dtype must be F32 or F64");
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    const dtans_encode_opts &o = *in;
+    if (o.layout < DTANS_LAYOUT_AUTO || o.layout > DTANS_LAYOUT_NNZ)
+        return set_err(DTANS_EINVAL, "layout must be AUTO, ROW or NNZ");
+    if (o.lane_nnz < 0 || o.lane_nnz % 4) return set_err(DTANS_EINVAL, "lane_nnz must be a multiple of 4");
+    if (o.waves_per_wg < 0 || o.waves_per_wg > 16 || o.wg_per_cu < 0 || o.wg_per_cu > 32)
+        return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return set_err(DTANS_EINVAL, "row_ptr must run from 0 to nnz");
+    for (int64_t i = 0; i < m; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return set_err(DTANS_EINVAL, "row_ptr decreases");
+    // encodings: the automatic choice first, then the other layout, then
+    // neighbouring lane lengths (x1/2, x2, x1/4, x4 of the automatic one)
+    int auto_layout = 0, auto_T = 0;
+    auto_encoding(m, nnz, row_ptr, o, auto_layout, auto_T);
+    std::vector<std::pair<int, int>> enc{{auto_layout, auto_T}};
+    auto add = [&](int lay, int T) {
+        for (auto &e : enc)
+            if (e.first == lay && e.second == T) return;
+        enc.push_back({lay, T});
+    };
+    if (o.layout == DTANS_LAYOUT_AUTO) {
+        dtans_encode_opts nn = o;
+        nn.layout = DTANS_LAYOUT_NNZ;
+        int lay = 0, T0 = 0;
+        auto_encoding(m, nnz, row_ptr, nn, lay, T0);
+        add(DTANS_LAYOUT_ROW, 0);
+        add(DTANS_LAYOUT_NNZ, T0);
+    }
+    const bool nnz_possible = o.layout != DTANS_LAYOUT_ROW;
+    if (nnz_possible && o.lane_nnz == 0) {
+        dtans_encode_opts nn = o;
+        nn.layout = DTANS_LAYOUT_NNZ;
+        int lay = 0, T0 = 0;
+        auto_encoding(m, nnz, row_ptr, nn, lay, T0);
+        for (int f : {-2, 2, -4, 4}) {
+            int T = f > 0 ? T0 * f : T0 / -f;
+            T = std::min(512, std::max(32, (T + 3) / 4 * 4));
+            add(DTANS_LAYOUT_NNZ, T);
+        }
+    }
+    for (auto &e : enc)
+        for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu)) {
+            dtans_encode_opts c = o;
+            c.layout = e.first;
+            c.lane_nnz = e.second;
+            c.waves_per_wg = w.first;
+            c.wg_per_cu = w.second;
+            out.push_back(c);
+        }
+    return DTANS_OK;
+}
+
+// 64-bit FNV-1a over 8-byte words (a fingerprint, not a checksum of record)
+struct Fingerprint {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void word(uint64_t w) {
+        h ^= w;
+        h *= 0x100000001b3ull;
+    }
+    void bytes(const void *p, size_t n) {
+        const uint8_t *b = (const uint8_t *)p;
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t w;
+            memcpy(&w, b + i, 8);
+            word(w);
+        }
+        uint64_t t = 0;
+        memcpy(&t, b + i, n - i);
+        word(t ^ ((uint64_t)(n - i) << 56));
+    }
+};
+
+struct TuneResources {
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    DevBufs bufs;
+    dtans_matrix *h = nullptr;
+    ~TuneResources() {
+        if (st) (void)hipStreamSynchronize(st);
+        if (h) dtans_destroy(h);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        bufs.release();
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -283,27 +428,10 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     }
     EncodeParams p;
     p.seed = o.perm_seed;
-    int layout = o.layout;
-    if (layout == DTANS_LAYOUT_AUTO) {
-        // one row per lane unless the rows are long or irregular enough that
-        // 64-row waves would be too few or badly balanced
-        int64_t maxlen = 0;
-        for (int64_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
-        double mean = m ? (double)nnz / m : 0;
-        int64_t waves = (m + 63) / 64;
-        layout = (waves < 2048 || maxlen > 8 * std::max(mean, 4.0)) ? DTANS_LAYOUT_NNZ : DTANS_LAYOUT_ROW;
-    }
+    int layout = 0, T = 0;
+    auto_encoding(m, nnz, row_ptr, o, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
-    if (p.layout == kLayoutNnz) {
-        int T = o.lane_nnz;
-        if (T == 0) {
-            // enough lanes for ~8 waves per SIMD of the device, 32..512 nonzeros each
-            int64_t lanes_target = 256LL * 4 * 8 * 64;
-            int64_t t = nnz / std::max<int64_t>(1, lanes_target);
-            T = (int)std::min<int64_t>(512, std::max<int64_t>(32, (t + 3) / 4 * 4));
-        }
-        p.lane_nnz = (uint32_t)T;
-    }
+    if (p.layout == kLayoutNnz) p.lane_nnz = (uint32_t)T;
     dtans_matrix *h = new dtans_matrix();
     std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c);
     if (!err.empty()) {
@@ -680,9 +808,160 @@ void dtans_csr_destroy(dtans_csr *h) {
     delete h;
 }
 
-dtans_status dtans_autotune(int64_t, int64_t, int64_t, const int32_t *, const int32_t *, const void *,
-                            dtans_dtype, int32_t, double, dtans_encode_opts *, double *) {
-    return set_err(DTANS_EUNSUPPORTED, "autotuner not built yet");
+int32_t dtans_autotune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr,
+                                  dtans_dtype dtype, int32_t k, const dtans_encode_opts *in,
+                                  dtans_encode_opts *out, int32_t cap) {
+    std::vector<dtans_encode_opts> c;
+    if (cap < 0 || (cap > 0 && !out)) {
+        set_err(DTANS_EINVAL, "out must hold cap >= 0 entries");
+        return -1;
+    }
+    if (tune_candidates(m, nnz, row_ptr, dtype, k, in, c) != DTANS_OK) return -1;
+    for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) out[i] = c[i];
+    return (int32_t)c.size();
+}
+
+dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, const void *vals, dtans_dtype dtype, int32_t k,
+                            double budget_s, const char *cache_path, dtans_encode_opts *inout,
+                            double *best_ms) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!inout) return set_err(DTANS_EINVAL, "inout is null");
+    if (!(budget_s >= 0)) return set_err(DTANS_EINVAL, "budget_s must be >= 0");
+    if (n < 0 || n >= (1ll << 31)) return set_err(DTANS_ERANGE, "columns must be 0..2^31-1");
+    if (nnz > 0 && (!col_idx || !vals)) return set_err(DTANS_EINVAL, "null array");
+    std::vector<dtans_encode_opts> cands;
+    dtans_status s = tune_candidates(m, nnz, row_ptr, dtype, k, inout, cands);
+    if (s) return s;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string devname = std::string(prop.name) + "/" + prop.gcnArchName;
+    for (char &ch : devname)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+
+    // fingerprint of the problem: sizes, dtype, k, the fixed options, the arrays
+    Fingerprint fp;
+    for (int64_t w : {m, n, nnz, (int64_t)dtype, (int64_t)k, (int64_t)inout->layout,
+                      (int64_t)inout->lane_nnz, (int64_t)inout->waves_per_wg,
+                      (int64_t)inout->wg_per_cu, (int64_t)inout->sort_rows})
+        fp.word((uint64_t)w);
+    fp.word(inout->perm_seed);
+    if (cache_path) {
+        fp.bytes(row_ptr, 4 * (size_t)(m + 1));
+        if (nnz > 0) {
+            fp.bytes(col_idx, 4 * (size_t)nnz);
+            fp.bytes(vals, (dtype == DTANS_F64 ? 8 : 4) * (size_t)nnz);
+        }
+        char key[17];
+        snprintf(key, sizeof key, "%016llx", (unsigned long long)fp.h);
+        if (FILE *f = fopen(cache_path, "r")) {
+            char line[1024];
+            while (fgets(line, sizeof line, f)) {
+                char tag[32], fk[32], dn[512];
+                int lay, T, w, g;
+                double ms;
+                if (sscanf(line, "%31s %31s %511s %d %d %d %d %lf", tag, fk, dn, &lay, &T, &w, &g,
+                           &ms) == 8 &&
+                    strcmp(tag, "dtans-autotune-v1") == 0 && strcmp(fk, key) == 0 && devname == dn) {
+                    fclose(f);
+                    inout->layout = lay;
+                    inout->lane_nnz = T;
+                    inout->waves_per_wg = w;
+                    inout->wg_per_cu = g;
+                    if (best_ms) *best_ms = ms;
+                    return DTANS_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+
+    TuneResources r;
+    HIP_TRY(hipStreamCreate(&r.st));
+    const size_t vb = dtype == DTANS_F64 ? 8 : 4;
+    void *X = nullptr, *Y = nullptr, *flush = nullptr;
+    HIP_TRY(r.bufs.upload(&X, nullptr, (size_t)std::max<int64_t>(n, 1) * k * vb, r.st));
+    HIP_TRY(r.bufs.upload(&Y, nullptr, (size_t)std::max<int64_t>(m, 1) * k * vb, r.st));
+    // x = 0x3f3f... bit patterns: finite, nonzero values of either width
+    HIP_TRY(hipMemsetAsync(X, 0x3f, (size_t)std::max<int64_t>(n, 1) * k * vb, r.st));
+    const int64_t flush_bytes = 512ll << 20;
+    HIP_TRY(r.bufs.upload(&flush, nullptr, flush_bytes, r.st));
+    uint32_t *sink = (uint32_t *)((char *)flush + flush_bytes);  // inside the 256-byte pad
+    const int kMaxReps = 25;
+    r.ev.resize(2 * kMaxReps);
+    for (auto &e : r.ev) HIP_TRY(hipEventCreate(&e));
+
+    double best = INFINITY;
+    dtans_encode_opts best_o = cands[0];
+    size_t i = 0;
+    while (i < cands.size()) {
+        double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (i > 0 && elapsed > budget_s) break;
+        // encode once for every launch shape of this encoding
+        dtans_encode_opts eo = cands[i];
+        eo.waves_per_wg = 0;
+        eo.wg_per_cu = 0;
+        if (r.h) {
+            dtans_destroy(r.h);
+            r.h = nullptr;
+        }
+        s = dtans_encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, &eo, &r.h);
+        if (s) return s;
+        s = dtans_to_device(r.h, r.st);
+        if (s) return s;
+        size_t j = i;
+        for (; j < cands.size() && cands[j].layout == cands[i].layout &&
+               cands[j].lane_nnz == cands[i].lane_nnz;
+             ++j) {
+            s = dtans_set_launch(r.h, cands[j].waves_per_wg, cands[j].wg_per_cu);
+            if (s) return s;
+            auto run = [&]() { return dtans_spmm(r.h, k, X, k, Y, k, 1.0, 0.0, r.st); };
+            // two untimed launches, then one timed to size the repetitions
+            for (int w = 0; w < 2; ++w)
+                if ((s = run())) return s;
+            HIP_TRY(launch_flush(flush, flush_bytes, sink, r.st));
+            HIP_TRY(hipEventRecord(r.ev[0], r.st));
+            if ((s = run())) return s;
+            HIP_TRY(hipEventRecord(r.ev[1], r.st));
+            HIP_TRY(hipEventSynchronize(r.ev[1]));
+            float probe = 0;
+            HIP_TRY(hipEventElapsedTime(&probe, r.ev[0], r.ev[1]));
+            // about 0.1 s of launches per shape (each rep also reads the flush buffer)
+            const int reps = (int)std::min<double>(kMaxReps, std::max(3.0, 100.0 / (probe + 0.15)));
+            for (int q = 0; q < reps; ++q) {
+                HIP_TRY(launch_flush(flush, flush_bytes, sink, r.st));
+                HIP_TRY(hipEventRecord(r.ev[2 * q], r.st));
+                if ((s = run())) return s;
+                HIP_TRY(hipEventRecord(r.ev[2 * q + 1], r.st));
+            }
+            HIP_TRY(hipStreamSynchronize(r.st));
+            std::vector<float> t(reps);
+            for (int q = 0; q < reps; ++q) HIP_TRY(hipEventElapsedTime(&t[q], r.ev[2 * q], r.ev[2 * q + 1]));
+            std::sort(t.begin(), t.end());
+            const double med = t[reps / 2];
+            if (med < best) {
+                best = med;
+                best_o = cands[j];
+            }
+        }
+        i = j;
+    }
+    inout->layout = best_o.layout;
+    inout->lane_nnz = best_o.lane_nnz;
+    inout->waves_per_wg = best_o.waves_per_wg;
+    inout->wg_per_cu = best_o.wg_per_cu;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (!f) return set_err(DTANS_EIO, std::string("cannot append to ") + cache_path);
+        int ok = fprintf(f, "dtans-autotune-v1 %016llx %s %d %d %d %d %.6f\n", (unsigned long long)fp.h,
+                         devname.c_str(), best_o.layout, best_o.lane_nnz, best_o.waves_per_wg,
+                         best_o.wg_per_cu, best);
+        if (fclose(f) != 0 || ok < 0) return set_err(DTANS_EIO, std::string("cannot write ") + cache_path);
+    }
+    return DTANS_OK;
 }
 
 }  // extern "C"

@@ -458,6 +458,16 @@ __global__ void scale_kernel(VT *Y, int64_t rows, int KC, int64_t ldy, double be
     *y = beta == 0.0 ? (VT)0 : (VT)(beta * (double)*y);
 }
 
+__global__ __launch_bounds__(256) void flush_kernel(const uint4 *p, int64_t n, uint32_t *sink) {
+    uint32_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 v = p[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads; the buffer is zero
+}
+
 // ------------------------------------------------- multi-matrix launch
 template <typename VT>
 __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha, double beta) {
@@ -874,6 +884,12 @@ hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, boo
         hipLaunchKernelGGL(batch_kernel<double>, dim3(L.grid), block, 0, st, b, alpha, beta);
     else
         hipLaunchKernelGGL(batch_kernel<float>, dim3(L.grid), block, 0, st, b, alpha, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush(const void *buf, int64_t bytes, uint32_t *sink, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(flush_kernel, dim3(2048), dim3(256), 0, st, (const uint4 *)buf, bytes / 16, sink);
     return hipGetLastError();
 }
 

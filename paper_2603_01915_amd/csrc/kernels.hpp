@@ -38,6 +38,10 @@ hipError_t launch_spmm_t(const DevMat &a, bool f64, int k, const void *dY, int64
 hipError_t launch_decode(const DevMat &a, bool f64, int32_t *col, void *vals, Launch L,
                          hipStream_t st);
 
+// read `bytes` (multiple of 16) of buf so that later launches find nothing of
+// theirs in L2 or the last-level cache; sink: one writable 32-bit word
+hipError_t launch_flush(const void *buf, int64_t bytes, uint32_t *sink, hipStream_t st);
+
 // many matrices (same dtype, layout ROW) in one persistent launch
 struct BatchTask {  // a contiguous run of waves of one matrix for one workgroup
     int32_t mat;

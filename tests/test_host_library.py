@@ -30,9 +30,10 @@ def rand_csr(m, n, dens, seed, dtype=np.float64, pool=None):
 def test_header_symbols_exported():
     """Every function declared in include/dtans.h is exported by libdtans.so."""
     text = open(os.path.join(ROOT, "include", "dtans.h")).read()
-    names = set(re.findall(r"^\s*(?:dtans_status|void|const char \*|int64_t)\s*\*?\s*(dtans_\w+)\s*\(",
-                           text, re.M))
-    assert len(names) == 23
+    names = set(re.findall(
+        r"^\s*(?:dtans_status|void|const char \*|int64_t|int32_t)\s*\*?\s*(dtans_\w+)\s*\(",
+        text, re.M))
+    assert len(names) == 24
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for n in sorted(names):
         assert hasattr(lib, n), n
@@ -197,3 +198,82 @@ def test_compression_closed_form_bound():
         A = P.Matrix.from_csr(rp, ci, v.astype(dt), 24 ** 3)
         inf = A.info()
         assert inf["csr_bytes"] / inf["stream_bytes"] <= bound
+
+
+def _auto_resolution(rp, ci, v, n, **kw):
+    """What dtans_encode_csr resolves for the given (partly automatic) options."""
+    A = P.Matrix.from_csr(rp, ci, v, n, **kw)
+    info = A.info()
+    return info["layout"], info["lane_nnz"]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_autotune_candidates_regular(dtype):
+    """A regular many-row matrix: the automatic encoding (row layout) comes
+    first with the launch shape the library picks by itself, the nonzero
+    layout follows with lane lengths around its automatic choice, and every
+    launch shape respects the CU's wave slots and LDS-limited workgroups."""
+    rp, ci, v = workloads.band(200_000, 8, 32, seed=3)
+    v = v.astype(dtype)
+    c = P.autotune_candidates(rp, len(ci), dtype)
+    assert c[0]["layout"] == P.LAYOUT_ROW and c[0]["lane_nnz"] == 0
+    lay, T = _auto_resolution(rp, ci, v, 200_000)
+    assert (lay, T) == (c[0]["layout"], c[0]["lane_nnz"])
+    A = P.Matrix.from_csr(rp, ci, v, 200_000)
+    assert A.info()["waves_per_wg"] == c[0]["waves_per_wg"]
+    maxwg = 2 if dtype == np.float64 else 3
+    assert c[0]["wg_per_cu"] == maxwg
+    keys = [(o["layout"], o["lane_nnz"], o["waves_per_wg"], o["wg_per_cu"]) for o in c]
+    assert len(set(keys)) == len(keys)
+    Ts = sorted({o["lane_nnz"] for o in c if o["layout"] == P.LAYOUT_NNZ})
+    assert len(Ts) >= 2 and all(t % 4 == 0 and 32 <= t <= 512 for t in Ts)
+    for o in c:
+        slots = 32 if o["layout"] == P.LAYOUT_ROW else 28
+        assert 1 <= o["wg_per_cu"] <= maxwg
+        assert 2 <= o["waves_per_wg"] <= min(16, slots // o["wg_per_cu"])
+    # encodings are grouped: each (layout, lane_nnz) appears in one run
+    runs = [k[:2] for i, k in enumerate(keys) if i == 0 or keys[i - 1][:2] != k[:2]]
+    assert len(runs) == len(set(runs))
+
+
+def test_autotune_candidates_small_and_fixed():
+    rp, ci, v = rand_csr(300, 200, 0.05, 2)
+    c = P.autotune_candidates(rp, len(ci))
+    lay, T = _auto_resolution(rp, ci, v, 200)
+    assert lay == P.LAYOUT_NNZ and (c[0]["layout"], c[0]["lane_nnz"]) == (lay, T)
+    # fixed fields are kept in every candidate
+    c = P.autotune_candidates(rp, len(ci), layout="nnz", wg_per_cu=1)
+    assert c and all(o["layout"] == P.LAYOUT_NNZ and o["wg_per_cu"] == 1 for o in c)
+    c = P.autotune_candidates(rp, len(ci), layout="row", waves_per_wg=4)
+    assert c and all(o["layout"] == P.LAYOUT_ROW and o["waves_per_wg"] == 4 for o in c)
+    c = P.autotune_candidates(rp, len(ci), layout="nnz", lane_nnz=64, waves_per_wg=8, wg_per_cu=2)
+    assert c == [{"layout": P.LAYOUT_NNZ, "lane_nnz": 64, "waves_per_wg": 8, "wg_per_cu": 2}]
+    # empty matrix: one encoding, still valid shapes
+    c = P.autotune_candidates(np.zeros(1, np.int32), 0)
+    assert c and c[0]["layout"] == P.LAYOUT_NNZ
+
+
+def test_autotune_candidates_errors():
+    rp, ci, v = rand_csr(50, 40, 0.1, 3)
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(rp, len(ci) + 1)            # row_ptr does not end at nnz
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(rp, len(ci), lane_nnz=6)     # not a multiple of 4
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(rp, len(ci), k=0)
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(rp, len(ci), waves_per_wg=17)
+    bad = rp.copy()
+    bad[10] = bad[11] + 1
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(bad, len(ci))
+
+
+def test_autotune_without_gpu_fails_loudly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; the GPU tests cover the autotuner")
+    rp, ci, v = rand_csr(64, 64, 0.1, 4)
+    with pytest.raises(P.DtansError) as e:
+        P.autotune(rp, ci, v, 64, budget_s=1.0)
+    assert e.value.status == _lib.EHIP
