@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--lane-nnz", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--stream-stage", type=int, default=0,
+                    help="row-layout SpMV: 0 auto, 1 direct word reads, 2 LDS ring")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -182,7 +184,8 @@ def main():
     log("encoding %d x %d, %d nonzeros" % (m, n, nnz))
     t0 = time.perf_counter()
     A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
-                           waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu)
+                           waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu,
+                           stream_stage=args.stream_stage)
     enc_s = time.perf_counter() - t0
     info = A0.info()
     log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
@@ -199,7 +202,7 @@ def main():
             A0.save(path)
             for _ in range(copies - 1):
                 B = P.Matrix.load(path)
-                B.set_launch(args.waves_per_wg, args.wg_per_cu)
+                B.set_launch(args.waves_per_wg, args.wg_per_cu, args.stream_stage)
                 mats.append(B)
     for A in mats:
         A.to_device()
@@ -230,7 +233,9 @@ def main():
         "dtype": "f64" if is64 else "f32", "data": "synthetic (seeded generator)",
         "config": {"workload": W["name"], "rows": m, "cols": n, "nnz": nnz, "k": k,
                    "layout": {1: "row", 2: "nnz"}[info["layout"]], "lane_nnz": info["lane_nnz"],
-                   "waves_per_wg": info["waves_per_wg"], "copies_rotated": copies},
+                   "waves_per_wg": info["waves_per_wg"],
+                   "stream_stage": {1: "direct", 2: "lds_ring"}[info["stream_stage"]],
+                   "copies_rotated": copies},
         "compressed_GBps": round(achieved, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,

@@ -61,13 +61,17 @@ typedef enum { DTANS_F32 = 1, DTANS_F64 = 2 } dtans_dtype;
  * summed by a fix-up pass.  AUTO lets the encoder choose. */
 typedef enum { DTANS_LAYOUT_AUTO = 0, DTANS_LAYOUT_ROW = 1, DTANS_LAYOUT_NNZ = 2 } dtans_layout;
 
+/* How the row-layout SpMV reads its word streams (dtans_encode_opts). */
+enum { DTANS_STAGE_AUTO = 0, DTANS_STAGE_DIRECT = 1, DTANS_STAGE_RING = 2 };
+
 typedef struct {
     int32_t layout;        /* dtans_layout */
     int32_t lane_nnz;      /* NNZ layout: nonzeros per lane, multiple of 4; 0 = auto */
     int32_t waves_per_wg;  /* kernel launch: wavefronts per workgroup (1..16); 0 = auto */
     int32_t wg_per_cu;     /* kernel launch: persistent workgroups per CU; 0 = auto */
     int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
-    int32_t reserved;
+    int32_t stream_stage;  /* ROW layout SpMV: 0 = auto, 1 = read stream words directly
+                              from device memory, 2 = stage them through an LDS ring */
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -86,6 +90,8 @@ typedef struct {
     double delta_entropy, value_entropy;   /* H of the delta / value distribution, bits (Eq. 1) */
     double delta_cross_entropy, value_cross_entropy; /* H(P, P') of the fitted tables (Eq. 2) */
     double bits_per_nnz;                   /* 8 * stream_bytes / nnz */
+    int32_t stream_stage;                  /* SpMV word reads: 1 direct, 2 LDS ring */
+    int32_t reserved;
 } dtans_info;
 
 typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */
@@ -124,7 +130,8 @@ dtans_status dtans_to_device(dtans_matrix *mat, void *stream);
 dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *out);
 
 /* Change the launch configuration of an encoded matrix (0 keeps the value). */
-dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu);
+dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu,
+                              int32_t stream_stage);
 
 /*
  * y = alpha * A x + beta * y (Sec. III-A; the paper's y = Ax is alpha=1,
@@ -158,8 +165,8 @@ dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_
                               void *stream);
 
 /*
- * Many matrices (at most 128, same dtype, ROW layout) in one persistent
- * launch: workgroups walk contiguous, cost-balanced runs of encoded waves and
+ * Many matrices (at most 128, same dtype, ROW layout, each x at most 4 GiB)
+ * in one persistent launch: workgroups walk contiguous, cost-balanced runs of encoded waves and
  * restage their LDS tables only when the matrix changes.  xs[i] / ys[i] are
  * device pointers for matrix i (host array of pointers, read during the
  * call).  The batch keeps a device table of these pointers that each call
@@ -198,10 +205,12 @@ void dtans_csr_destroy(dtans_csr *csr);
  * Autotuner (encode-time parameters; no equivalent in the paper, which uses
  * one fixed launch per GPU).  Candidate options are the fields of *in left at
  * 0 / AUTO, searched over: layout {ROW, NNZ}; for NNZ, nonzeros per lane
- * around the automatic choice (multiples of 4 between 32 and 512); and launch
- * shapes (workgroups per CU up to the LDS limit, waves per workgroup filling
- * the CU's wave slots, then half and a quarter of that).  Fields set in *in
- * are kept in every candidate.
+ * around the automatic choice (multiples of 4 between 32 and 512); for ROW,
+ * the stream stage (LDS ring with 16, 8 or 4 waves per workgroup and as many
+ * workgroups per CU as fit, then direct reads); and launch shapes of the
+ * direct-read kernels (workgroups per CU up to the LDS limit, waves per
+ * workgroup filling the CU's wave slots, then half and a quarter of that).
+ * Fields set in *in are kept in every candidate.
  *
  * dtans_autotune_candidates is host-only: it writes at most `cap` candidates,
  * in the order the autotuner times them (the automatic choice first), to out
@@ -218,7 +227,8 @@ void dtans_csr_destroy(dtans_csr *csr);
  * multiplication to *best_ms.  cache_path (may be NULL) names a text file of
  * earlier results, one line per (matrix fingerprint, dtype, k, fixed options,
  * device name): a hit returns the stored options without encoding; a new
- * result is appended.  Needs a GPU; blocks until its work is done.
+ * result is appended (a file that cannot be written gives DTANS_EIO after
+ * *inout is filled).  Needs a GPU; blocks until its work is done.
  */
 int32_t dtans_autotune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr,
                                   dtans_dtype dtype, int32_t k, const dtans_encode_opts *in,

@@ -20,10 +20,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import DtansError, EncodeOpts, Info, LAYOUT_AUTO, LAYOUT_NNZ, LAYOUT_ROW
+from ._lib import (DtansError, EncodeOpts, Info, LAYOUT_AUTO, LAYOUT_NNZ, LAYOUT_ROW, STAGE_AUTO,
+                   STAGE_DIRECT, STAGE_RING)
 
 __all__ = ["Matrix", "CsrBaseline", "Batch", "DtansError", "autotune", "autotune_candidates", "version",
-           "LAYOUT_AUTO", "LAYOUT_ROW", "LAYOUT_NNZ"]
+           "LAYOUT_AUTO", "LAYOUT_ROW", "LAYOUT_NNZ", "STAGE_AUTO", "STAGE_DIRECT", "STAGE_RING"]
 
 _LAYOUTS = {"auto": LAYOUT_AUTO, "row": LAYOUT_ROW, "nnz": LAYOUT_NNZ,
             LAYOUT_AUTO: LAYOUT_AUTO, LAYOUT_ROW: LAYOUT_ROW, LAYOUT_NNZ: LAYOUT_NNZ}
@@ -97,7 +98,7 @@ class Matrix:
     @classmethod
     def from_csr(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
                  waves_per_wg: int = 0, wg_per_cu: int = 0, sort_rows: bool = False,
-                 seed: int = 1) -> "Matrix":
+                 seed: int = 1, stream_stage: int = 0) -> "Matrix":
         L = _lib.load()
         rp = _np(row_ptr, np.int32)
         ci = _np(col, np.int32)
@@ -113,6 +114,7 @@ class Matrix:
         o.wg_per_cu = wg_per_cu
         o.sort_rows = int(bool(sort_rows))
         o.perm_seed = seed
+        o.stream_stage = stream_stage
         h = ctypes.c_void_p()
         _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
                                       ctypes.byref(o), ctypes.byref(h)))
@@ -150,8 +152,8 @@ class Matrix:
         torch = _torch()
         return torch.float64 if self.is_f64 else torch.float32
 
-    def set_launch(self, waves_per_wg: int = 0, wg_per_cu: int = 0) -> None:
-        _lib.check(self._L.dtans_set_launch(self._h, waves_per_wg, wg_per_cu))
+    def set_launch(self, waves_per_wg: int = 0, wg_per_cu: int = 0, stream_stage: int = 0) -> None:
+        _lib.check(self._L.dtans_set_launch(self._h, waves_per_wg, wg_per_cu, stream_stage))
 
     def to_device(self, stream=None) -> "Matrix":
         _lib.check(self._L.dtans_to_device(self._h, ctypes.c_void_p(_stream(stream))))
@@ -326,13 +328,15 @@ class Batch:
             pass
 
 
-def _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows=False, perm_seed=1):
+def _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, stream_stage=0, sort_rows=False,
+               perm_seed=1):
     o = EncodeOpts()
     _lib.load().dtans_default_opts(ctypes.byref(o))
     o.layout = _LAYOUTS[layout]
     o.lane_nnz = lane_nnz
     o.waves_per_wg = waves_per_wg
     o.wg_per_cu = wg_per_cu
+    o.stream_stage = stream_stage
     o.sort_rows = int(bool(sort_rows))
     o.perm_seed = perm_seed
     return o
@@ -340,15 +344,16 @@ def _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows=False, perm_
 
 def _opts_dict(o) -> dict:
     return {"layout": o.layout, "lane_nnz": o.lane_nnz, "waves_per_wg": o.waves_per_wg,
-            "wg_per_cu": o.wg_per_cu}
+            "wg_per_cu": o.wg_per_cu, "stream_stage": o.stream_stage}
 
 
 def autotune_candidates(row_ptr, nnz: int, dtype=np.float64, k: int = 1, layout="auto",
-                        lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0):
+                        lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0,
+                        stream_stage: int = 0):
     """The options ``autotune`` would time, in its order (host only)."""
     L = _lib.load()
     rp = _np(row_ptr, np.int32)
-    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu)
+    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, stream_stage)
     code = _lib.F64 if np.dtype(dtype) == np.float64 else _lib.F32
     cnt = L.dtans_autotune_candidates(len(rp) - 1, nnz, _ptr(rp), code, k, ctypes.byref(o), None, 0)
     if cnt < 0:
@@ -360,7 +365,7 @@ def autotune_candidates(row_ptr, nnz: int, dtype=np.float64, k: int = 1, layout=
 
 def autotune(row_ptr, col, vals, n: int, k: int = 1, budget_s: float = 20.0,
              layout="auto", lane_nnz: int = 0, waves_per_wg: int = 0, wg_per_cu: int = 0,
-             cache: str | None = None):
+             stream_stage: int = 0, cache: str | None = None):
     """Search layout, nonzeros per lane and launch shape on the current GPU.
     Returns (options dict for ``Matrix.from_csr``, best milliseconds per
     multiplication).  ``cache``: optional text file of earlier results."""
@@ -370,7 +375,7 @@ def autotune(row_ptr, col, vals, n: int, k: int = 1, budget_s: float = 20.0,
     v = _np(vals)
     if v.dtype not in (np.float32, np.float64):
         v = v.astype(np.float64)
-    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu)
+    o = _tune_opts(layout, lane_nnz, waves_per_wg, wg_per_cu, stream_stage)
     best = ctypes.c_double()
     _lib.check(L.dtans_autotune(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
                                 _dtype_code(v), k, budget_s,

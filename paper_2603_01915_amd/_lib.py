@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdtans.so")
 OK, EINVAL, EUNSORTED, ERANGE, ENOMEM, EHIP, ECORRUPT, EUNSUPPORTED, EIO = range(9)
 F32, F64 = 1, 2
 LAYOUT_AUTO, LAYOUT_ROW, LAYOUT_NNZ = 0, 1, 2
+STAGE_AUTO, STAGE_DIRECT, STAGE_RING = 0, 1, 2
 
 _NAMES = {EINVAL: "EINVAL", EUNSORTED: "EUNSORTED", ERANGE: "ERANGE", ENOMEM: "ENOMEM",
           EHIP: "EHIP", ECORRUPT: "ECORRUPT", EUNSUPPORTED: "EUNSUPPORTED", EIO: "EIO"}
@@ -30,7 +31,7 @@ class DtansError(RuntimeError):
 class EncodeOpts(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("lane_nnz", ctypes.c_int32),
                 ("waves_per_wg", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("sort_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sort_rows", ctypes.c_int32), ("stream_stage", ctypes.c_int32),
                 ("perm_seed", ctypes.c_uint64)]
 
 
@@ -47,7 +48,8 @@ class Info(ctypes.Structure):
                 ("delta_symbols", ctypes.c_int32), ("value_symbols", ctypes.c_int32),
                 ("delta_entropy", ctypes.c_double), ("value_entropy", ctypes.c_double),
                 ("delta_cross_entropy", ctypes.c_double),
-                ("value_cross_entropy", ctypes.c_double), ("bits_per_nnz", ctypes.c_double)]
+                ("value_cross_entropy", ctypes.c_double), ("bits_per_nnz", ctypes.c_double),
+                ("stream_stage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -65,7 +67,7 @@ SIGNATURES = {
     "dtans_load": (_I32, [_S, _PP]),
     "dtans_to_device": (_I32, [_P, _P]),
     "dtans_matrix_info": (_I32, [_P, ctypes.POINTER(Info)]),
-    "dtans_set_launch": (_I32, [_P, _I32, _I32]),
+    "dtans_set_launch": (_I32, [_P, _I32, _I32, _I32]),
     "dtans_spmv": (_I32, [_P, _P, _P, _D, _D, _P]),
     "dtans_spmm": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
     "dtans_spmm_t": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),

@@ -86,7 +86,7 @@ struct dtans_matrix {
     DevBufs bufs;
     bool uploaded = false;
     int device = -1, num_cus = 256;
-    int waves_per_wg = 0, wg_per_cu = 0;
+    int waves_per_wg = 0, wg_per_cu = 0, stage = 0;
     DevMat view{};
     double *partial = nullptr;
     size_t partial_cap = 0;  // doubles
@@ -115,6 +115,13 @@ struct dtans_csr {
 
 namespace {
 
+// SpMV of the row layout stages its streams through an LDS ring unless told
+// not to; a wavefront's run of streams is addressed with 32-bit offsets.
+bool uses_ring(const dtans_matrix *h) {
+    return h->c.layout == kLayoutRow && h->stage != DTANS_STAGE_DIRECT &&
+           4 * (int64_t)h->c.words.size() < (1ll << 31);
+}
+
 Launch plan_launch(const dtans_matrix *h) {
     const bool f64 = h->c.dtype == kF64;
     const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
@@ -130,6 +137,13 @@ Launch plan_launch(const dtans_matrix *h) {
     int64_t need = (h->c.num_waves + wpw - 1) / wpw;
     int64_t grid = (int64_t)h->num_cus * wgcu;
     L.grid = (int)std::max<int64_t>(1, std::min(grid, need));
+    L.num_cus = h->num_cus;
+    L.ring = uses_ring(h) ? 1 : 0;
+    if (L.ring) {
+        // one 16-wave workgroup per CU; the launch adds as many as fit
+        L.waves_per_wg = h->waves_per_wg > 0 ? h->waves_per_wg : 16;
+        L.wg_per_cu = h->wg_per_cu;
+    }
     return L;
 }
 
@@ -327,15 +341,30 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
             add(DTANS_LAYOUT_NNZ, T);
         }
     }
-    for (auto &e : enc)
-        for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu)) {
+    if (o.stream_stage < 0 || o.stream_stage > DTANS_STAGE_RING)
+        return set_err(DTANS_EINVAL, "stream_stage must be 0, 1 or 2");
+    for (auto &e : enc) {
+        auto push = [&](int w, int g, int stage) {
             dtans_encode_opts c = o;
             c.layout = e.first;
             c.lane_nnz = e.second;
-            c.waves_per_wg = w.first;
-            c.wg_per_cu = w.second;
+            c.waves_per_wg = w;
+            c.wg_per_cu = g;
+            c.stream_stage = stage;
             out.push_back(c);
+        };
+        const bool row = e.first == DTANS_LAYOUT_ROW;
+        // row layout: the LDS-ring SpMV (its own shapes; workgroups per CU as
+        // many as fit unless fixed) before the direct-read one
+        if (row && o.stream_stage != DTANS_STAGE_DIRECT) {
+            if (o.waves_per_wg) push(o.waves_per_wg, o.wg_per_cu, DTANS_STAGE_RING);
+            else
+                for (int w : {16, 8, 4}) push(w, o.wg_per_cu, DTANS_STAGE_RING);
         }
+        if (!row || o.stream_stage != DTANS_STAGE_RING)
+            for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu))
+                push(w.first, w.second, row ? DTANS_STAGE_DIRECT : o.stream_stage);
+    }
     return DTANS_OK;
 }
 
@@ -403,6 +432,8 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null array");
     if (o.waves_per_wg < 0 || o.waves_per_wg > 16 || o.wg_per_cu < 0 || o.wg_per_cu > 32)
         return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
+    if (o.stream_stage < 0 || o.stream_stage > DTANS_STAGE_RING)
+        return set_err(DTANS_EINVAL, "stream_stage must be 0, 1 or 2");
     const size_t vb = dtype == DTANS_F64 ? 8 : 4;
     std::vector<int32_t> scol;
     std::vector<uint8_t> sval;
@@ -440,6 +471,7 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     }
     h->waves_per_wg = o.waves_per_wg;
     h->wg_per_cu = o.wg_per_cu;
+    h->stage = o.stream_stage;
     *out = h;
     return DTANS_OK;
 }
@@ -467,12 +499,16 @@ dtans_status dtans_to_device(dtans_matrix *mat, void *stream) {
     return check_handle(mat, (hipStream_t)stream);
 }
 
-dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu) {
+dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu,
+                              int32_t stream_stage) {
     if (!mat) return set_err(DTANS_EINVAL, "null matrix handle");
     if (waves_per_wg < 0 || waves_per_wg > 16 || wg_per_cu < 0 || wg_per_cu > 32)
         return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
+    if (stream_stage < 0 || stream_stage > DTANS_STAGE_RING)
+        return set_err(DTANS_EINVAL, "stream_stage must be 0, 1 or 2");
     if (waves_per_wg) mat->waves_per_wg = waves_per_wg;
     if (wg_per_cu) mat->wg_per_cu = wg_per_cu;
+    if (stream_stage) mat->stage = stream_stage;
     return DTANS_OK;
 }
 
@@ -514,6 +550,7 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->delta_cross_entropy = c.dtab.cross_entropy;
     o->value_cross_entropy = c.vtab.cross_entropy;
     o->bits_per_nnz = c.nnz ? 8.0 * o->stream_bytes / c.nnz : 0.0;
+    o->stream_stage = uses_ring(mat) ? DTANS_STAGE_RING : DTANS_STAGE_DIRECT;
     return DTANS_OK;
 }
 
@@ -589,6 +626,8 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
         if ((mats[i]->c.dtype == kF64) != f64) return set_err(DTANS_EINVAL, "batch matrices must share a dtype");
         if (mats[i]->c.layout != kLayoutRow)
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must use the ROW layout");
+        if (mats[i]->c.n * (int64_t)mats[i]->c.value_bytes() > (1ll << 32))
+            return set_err(DTANS_EUNSUPPORTED, "batch matrices must have x of at most 4 GiB");
         dtans_status s = upload(mats[i], nullptr);
         if (s) return s;
         if (mats[i]->device != mats[0]->device) return set_err(DTANS_EINVAL, "batch matrices on different devices");
@@ -845,7 +884,8 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
     Fingerprint fp;
     for (int64_t w : {m, n, nnz, (int64_t)dtype, (int64_t)k, (int64_t)inout->layout,
                       (int64_t)inout->lane_nnz, (int64_t)inout->waves_per_wg,
-                      (int64_t)inout->wg_per_cu, (int64_t)inout->sort_rows})
+                      (int64_t)inout->wg_per_cu, (int64_t)inout->sort_rows,
+                      (int64_t)inout->stream_stage})
         fp.word((uint64_t)w);
     fp.word(inout->perm_seed);
     if (cache_path) {
@@ -860,16 +900,17 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
             char line[1024];
             while (fgets(line, sizeof line, f)) {
                 char tag[32], fk[32], dn[512];
-                int lay, T, w, g;
+                int lay, T, w, g, st;
                 double ms;
-                if (sscanf(line, "%31s %31s %511s %d %d %d %d %lf", tag, fk, dn, &lay, &T, &w, &g,
-                           &ms) == 8 &&
-                    strcmp(tag, "dtans-autotune-v1") == 0 && strcmp(fk, key) == 0 && devname == dn) {
+                if (sscanf(line, "%31s %31s %511s %d %d %d %d %d %lf", tag, fk, dn, &lay, &T, &w, &g,
+                           &st, &ms) == 9 &&
+                    strcmp(tag, "dtans-autotune-v2") == 0 && strcmp(fk, key) == 0 && devname == dn) {
                     fclose(f);
                     inout->layout = lay;
                     inout->lane_nnz = T;
                     inout->waves_per_wg = w;
                     inout->wg_per_cu = g;
+                    inout->stream_stage = st;
                     if (best_ms) *best_ms = ms;
                     return DTANS_OK;
                 }
@@ -915,7 +956,8 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
         for (; j < cands.size() && cands[j].layout == cands[i].layout &&
                cands[j].lane_nnz == cands[i].lane_nnz;
              ++j) {
-            s = dtans_set_launch(r.h, cands[j].waves_per_wg, cands[j].wg_per_cu);
+            s = dtans_set_launch(r.h, cands[j].waves_per_wg, cands[j].wg_per_cu,
+                                 cands[j].stream_stage);
             if (s) return s;
             auto run = [&]() { return dtans_spmm(r.h, k, X, k, Y, k, 1.0, 0.0, r.st); };
             // two untimed launches, then one timed to size the repetitions
@@ -952,13 +994,14 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
     inout->lane_nnz = best_o.lane_nnz;
     inout->waves_per_wg = best_o.waves_per_wg;
     inout->wg_per_cu = best_o.wg_per_cu;
+    inout->stream_stage = best_o.stream_stage;
     if (best_ms) *best_ms = best;
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (!f) return set_err(DTANS_EIO, std::string("cannot append to ") + cache_path);
-        int ok = fprintf(f, "dtans-autotune-v1 %016llx %s %d %d %d %d %.6f\n", (unsigned long long)fp.h,
-                         devname.c_str(), best_o.layout, best_o.lane_nnz, best_o.waves_per_wg,
-                         best_o.wg_per_cu, best);
+        int ok = fprintf(f, "dtans-autotune-v2 %016llx %s %d %d %d %d %d %.6f\n",
+                         (unsigned long long)fp.h, devname.c_str(), best_o.layout, best_o.lane_nnz,
+                         best_o.waves_per_wg, best_o.wg_per_cu, best_o.stream_stage, best);
         if (fclose(f) != 0 || ok < 0) return set_err(DTANS_EIO, std::string("cannot write ") + cache_path);
     }
     return DTANS_OK;

@@ -16,6 +16,7 @@
 // ranges, which keeps their x gathers in the same L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "dtans_core.hpp"
@@ -26,6 +27,7 @@ namespace {
 
 constexpr int kComplete = 0, kHead = 1, kTail = 2;
 constexpr int kNumXcd = 8;
+constexpr int kRingWords = 1024;  // per-wavefront LDS ring of the ring kernels (4 KiB)
 
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -61,13 +63,18 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// y (k columns) = alpha * A x + beta * y.  UNIT: k = 1 with unit strides.
+// y (k columns) = alpha * A x + beta * y.  UNIT: k = 1 with unit strides and
+// n * sizeof(VT) <= 2^32.
 // ACC: accumulator type.  double everywhere except FP32 SpMM with many
 // columns in the nonzero-balanced layout, where a lane sums a bounded number
 // of nonzeros (at most 1024; measured error ~1e-7 of |A||x| at 512) before
 // its partial sums are combined in double.
-template <typename VT, int KC, bool UNIT, typename ACC = double>
+// DEFER (lanes holding single rows, KC <= 4): a segment's x values are
+// loaded when it arrives and multiplied when the next segment arrives or the
+// row ends, so their latency overlaps one decoding step.
+template <typename VT, int KC, bool UNIT, typename ACC = double, bool DEFER = false>
 struct SpmmSink {
+    static_assert(!DEFER || KC <= 4, "deferred products keep 4*KC x values in registers");
     static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
     struct Params {
         const VT *X;
@@ -81,15 +88,42 @@ struct SpmmSink {
     int64_t lane;
     int32_t cur, head_row;  // row being accumulated; the lane's head row or -1
     ACC acc[KC];
+    VT pv[DEFER ? 4 : 1], px[DEFER ? 4 : 1][KC];  // deferred segment
+    int pn;                                       // its nonzeros (0: none)
     // cur starts at -1: a row is finished only after the sink has seen one of
     // its nonzeros (empty rows are written by the decoder via empty_row)
     __device__ SpmmSink(const Params &pp, int64_t l, int32_t first_row, bool first_is_head)
-        : p(pp), lane(l), cur(-1), head_row(first_is_head ? first_row : -1) {
+        : p(pp), lane(l), cur(-1), head_row(first_is_head ? first_row : -1), pn(0) {
 #pragma unroll
         for (int c = 0; c < KC; ++c) acc[c] = (ACC)0;
     }
+    // multiply the deferred segment (its x loads were issued a step ago)
+    __device__ __forceinline__ void consume() {
+        if constexpr (DEFER) {
+            if (!ballot(pn < 4)) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)pv[k], (ACC)px[k][c], acc[c]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) {
+                        const ACC t = fma((ACC)pv[k], (ACC)px[k][c], acc[c]);
+                        acc[c] = k < pn ? t : acc[c];
+                    }
+            }
+            pn = 0;
+        }
+    }
+    // called once per decoding step before the step issues any loads
+    __device__ __forceinline__ void pre_step() { consume(); }
+    // UNIT: x spans at most 4 GiB, so a 32-bit byte offset from the uniform
+    // base addresses it (one shift per gather, base in SGPRs)
     __device__ __forceinline__ const VT *xrow(uint32_t col) const {
-        return UNIT ? p.X + col : p.X + (uint64_t)col * p.ldx;
+        return UNIT ? (const VT *)((const char *)p.X + col * (uint32_t)sizeof(VT))
+                    : p.X + (uint64_t)col * p.ldx;
     }
     __device__ __forceinline__ void store(int32_t row, int kind) {
         if (kind == kComplete) {
@@ -109,6 +143,28 @@ struct SpmmSink {
     template <bool MULTI>
     __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
                                             int64_t, const int32_t rowk[4]) {
+        if constexpr (DEFER) {
+            if constexpr (!MULTI) {
+                // every lane loads four x values (column 0 stands in for
+                // nonzeros past the lane's end; their products are dropped)
+                uint32_t cc[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) cc[k] = col[k];
+                if (ballot(nreal < 4)) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) cc[k] = k < nreal ? col[k] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) px[k][c] = xrow(cc[k])[c];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pv[k] = v[k];
+                pn = nreal;
+                return;
+            }
+            consume();
+        }
         if (KC <= 4) {
             VT x[4][KC];
             if (nreal >= 4 && (!MULTI || rowk[3] == cur)) {  // common case: no tail, no row end
@@ -163,7 +219,10 @@ struct SpmmSink {
             }
         }
     }
-    __device__ __forceinline__ void finish_row(int32_t row, int kind) { store(row, kind); }
+    __device__ __forceinline__ void finish_row(int32_t row, int kind) {
+        consume();
+        store(row, kind);
+    }
     __device__ __forceinline__ void empty_row(int32_t row) {
         VT *y = UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy;
 #pragma unroll
@@ -206,6 +265,7 @@ struct TransSink {
                 for (int c = 0; c < KC; ++c) unsafeAtomicAdd(dst + c, v[k] * dy[c]);
             }
     }
+    __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
     __device__ __forceinline__ void empty_row(int32_t) {}
 };
@@ -230,17 +290,121 @@ struct DecodeSink {
                 p.vals[g + k] = __builtin_bit_cast(typename Bits<VT>::T, v[k]);
             }
     }
+    __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
     __device__ __forceinline__ void empty_row(int32_t) {}
 };
 
 // --------------------------------------------------------- wave decoding
+// Word sources.  A decoder reads the words of its wave's stream at 32-bit
+// byte offsets that are wave-uniform plus a lane prefix.
+//
+// GlobalWords reads them from device memory: every step's loads depend on the
+// previous step's ballots, so each step waits for one memory round trip.
+struct GlobalWords {
+    const char *W;  // stream base of the current encoded wave
+    __device__ __forceinline__ uint32_t word(uint32_t off) const {
+        return *(const uint32_t *)(W + off);
+    }
+    __device__ __forceinline__ void step_begin() {}
+    __device__ __forceinline__ void consumed(uint32_t) {}
+};
+
+// RingWords stages a contiguous run of streams (the encoded waves [a, b) of
+// one wavefront are adjacent in memory) through a per-wavefront ring of kRing
+// words in LDS.  Chunks of 1 KiB (one aligned 16-byte load per lane) are requested
+// as soon as the ring has room and written into it at the start of the next
+// step, so the words a step reads were loaded at least one step earlier and
+// the decode's serial chain runs through LDS only.  Invariant: chunks are
+// requested in order, at most one per step, and written one step later,
+// after that step's reads; a step reads at most 768 bytes (three words per
+// lane) < one chunk, so the requested end stays at least kRing*4 - 1 KiB
+// ahead of the read position, and the words a step reads were requested two
+// steps earlier: kRing*4 - 1 KiB >= 2 * 768 + 768 bytes suffices.  A chunk
+// overwrites only words already read.  LDS operations of one wavefront
+// complete in order, so no barrier is needed between chunk writes and reads.
+template <int kRing>
+struct RingWords {
+    static constexpr uint32_t kChunk = 1024;
+    static_assert(kRing * 4 >= (int)kChunk + 3 * 768, "ring too small for two steps of lead");
+    uint32_t *ring;     // this wavefront's ring (kRing words)
+    const char *base;   // the run's first word rounded down to 16 bytes
+    uint32_t skew;      // bytes from base to the run's first word (0..12)
+    uint32_t total;     // skew + bytes in the run
+    uint32_t fetched;   // bytes from base requested so far (multiple of kChunk)
+    uint32_t pend_at;   // offset from base of the chunk in flight
+    bool has_pend;
+    uint4 pend;         // this lane's 16 bytes of the chunk in flight
+    uint32_t lane;
+
+    // 16-byte aligned loads; the last one of a run passes its end by at most
+    // 15 bytes, which stay inside the padded word buffer.  Lanes past the end
+    // reload the run's first 16 bytes (unconditional loads keep the wait
+    // counts static); what they write to the ring is never read.
+    __device__ __forceinline__ uint4 load_chunk_part(uint32_t at) const {
+        const uint32_t o = at + 16 * lane;
+        return *(const uint4 *)(base + (o < total ? o : 0u));
+    }
+    __device__ __forceinline__ void write_chunk_part(uint32_t at, uint4 v) {
+        *(uint4 *)(ring + (((at >> 2) + 4 * lane) & (kRing - 1))) = v;
+    }
+    __device__ __forceinline__ void start(uint32_t *r, const uint32_t *first, uint32_t bytes,
+                                          uint32_t ln) {
+        ring = r;
+        skew = (uint32_t)((uintptr_t)first & 15);
+        base = (const char *)first - skew;
+        total = skew + bytes;
+        lane = ln;
+        fetched = 0;
+        has_pend = false;
+        // fill the whole ring before the first read
+#pragma unroll
+        for (int c = 0; c < kRing * 4 / (int)kChunk; ++c) {
+            if (fetched < total) {
+                write_chunk_part(fetched, load_chunk_part(fetched));
+                fetched += kChunk;
+            }
+        }
+    }
+    // off: bytes from the run's first word
+    __device__ __forceinline__ uint32_t word(uint32_t off) const {
+        return ring[((off + skew) >> 2) & (kRing - 1)];
+    }
+    __device__ __forceinline__ void step_begin() {
+        if (has_pend) {
+            write_chunk_part(pend_at, pend);
+            has_pend = false;
+        }
+    }
+    // the decoder's read position has advanced to pos (bytes from the run's
+    // first word); request the next chunk once the ring has room for it
+    __device__ __forceinline__ void consumed(uint32_t pos) {
+        if (fetched < total && fetched + kChunk <= pos + skew + kRing * 4) {
+            pend = load_chunk_part(fetched);
+            pend_at = fetched;
+            has_pend = true;
+            fetched += kChunk;
+        }
+    }
+};
+
+// Read positions of a stream: words (bytes), escaped deltas and escaped values
+// (counts), with the escape region bases.  A cursor restarts at every encoded
+// wave for GlobalWords and runs on across a run for RingWords.
+template <typename VT>
+struct Cursor {
+    uint32_t pos, dpos, vpos;
+    const uint32_t *ED;
+    const VT *EV;
+};
+
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
 // nonzeros of this thread's lane to a sink constructed here.
-template <int LAYOUT, typename VT, class Sink>
+template <int LAYOUT, typename VT, class Sink, class Src>
 __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
                                              const VT *__restrict__ tval, int64_t slice,
-                                             uint32_t lane, const typename Sink::Params &sp) {
+                                             uint32_t lane, const typename Sink::Params &sp,
+                                             Src &src, Cursor<VT> &cur) {
     const int64_t l = slice * kWave + lane;
     const bool live = l < a.num_lanes;
     int64_t g0 = 0;
@@ -263,24 +427,25 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     }
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
     const int S = (cnt + 3) >> 2;
-    const int Smax = wave_max(S);
+    const int Smax = __builtin_amdgcn_readfirstlane(wave_max(S));  // uniform: scalar loop
 
-    // per-wave stream bases are uniform; offsets into them are 32-bit byte
-    // offsets that stay uniform (popcounts of ballots) and live in SGPRs
-    const char *__restrict__ W = (const char *)(a.words + a.woff[slice]);
-    const uint32_t *__restrict__ ED = a.escd + a.doff[slice];
-    const VT *__restrict__ EV = (const VT *)a.escv + a.voff[slice];
-    auto word = [&](uint32_t byte_off) { return *(const uint32_t *)(W + byte_off); };
-    uint32_t pos, dpos = 0, vpos = 0;
+    // stream offsets are 32-bit and wave-uniform (popcounts of ballots), so
+    // they live in SGPRs
+    uint32_t pos = cur.pos, dpos = cur.dpos, vpos = cur.vpos;
+    const uint32_t *__restrict__ ED = cur.ED;
+    const VT *__restrict__ EV = cur.EV;
+    auto word = [&](uint32_t byte_off) { return src.word(byte_off); };
     uint32_t w1, w2, w3;
     {
         // lanes without a stream read a neighbouring word (buffers are padded)
         const uint64_t mk = ballot(S > 0);
         const uint32_t pre = 4 * lane_prefix(mk), c = 4 * (uint32_t)__popcll(mk);
-        w1 = word(pre);
-        w2 = word(c + pre);
-        w3 = word(2 * c + pre);
-        pos = 3 * c;
+        w1 = word(pos + pre);
+        w2 = word(pos + c + pre);
+        w3 = word(pos + 2 * c + pre);
+        pos += 3 * c;
+        src.step_begin();
+        src.consumed(pos);
     }
     uint32_t d = 0, r = 1, col = 0;
     int64_t g = g0;
@@ -308,9 +473,11 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             group4((uint32_t)(e[4] >> 32) & 0xffffu, (uint32_t)(e[5] >> 48),
                    (uint32_t)(e[6] >> 32) & 0xffffu, (uint32_t)(e[7] >> 48), D, Rm1);
             const bool ext2 = append_and_check(d, r, D, Rm1, x2);
-            const uint64_t m1 = ballot(more && !ext1);
-            const uint64_t m2 = ballot(more && !ext2);
+            // masks combined on the scalar unit: a ballot of a plain compare
+            // is the compare's own lane mask
             const uint64_t m3 = ballot(more);
+            const uint64_t m1 = m3 & ~ballot(ext1);
+            const uint64_t m2 = m3 & ~ballot(ext2);
             const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
             const uint32_t l1 = word(pos + 4 * lane_prefix(m1));
             const uint32_t l2 = word(pos + c1 + 4 * lane_prefix(m2));
@@ -320,15 +487,26 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             w2 = ext2 ? x2 : l2;
             w3 = l3;
         }
+        // deferred products of the previous step and the ring's pending chunk
+        // first, then this step's escapes (loaded and waited for at once),
+        // then the next chunk and this step's x loads, which the next step
+        // waits for: a step waits on memory for loads issued a step earlier
+        sink.pre_step();
+        src.step_begin();
+        // escape flags: bit 31 of a delta slot's entry, bit 30 of a value
+        // slot's entry.  When no active lane has either bit set in any of its
+        // eight entries (the common case) the low words are the deltas as they
+        // are; otherwise the flags are masked off and the escapes read.
+        // Padding symbols are never escapes, so only lanes past their last
+        // segment need masking.
         uint32_t dl[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k] & (kDeltaLimit - 1);
-        // escape flags: bit 31 of a delta slot's word, bit 30 of a value
-        // slot's word.  Padding symbols are never escapes, so only lanes past
-        // their last segment need masking.
-        const uint32_t escd_any = (uint32_t)e[0] | (uint32_t)e[2] | (uint32_t)e[4] | (uint32_t)e[6];
-        const uint32_t escv_any = (uint32_t)e[1] | (uint32_t)e[3] | (uint32_t)e[5] | (uint32_t)e[7];
-        if (ballot(act && (((escd_any >> 1) | escv_any) & (1u << 30)))) {  // wave-uniform
+        for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k];
+        const uint32_t flags = (uint32_t)e[0] | (uint32_t)e[1] | (uint32_t)e[2] | (uint32_t)e[3] |
+                               (uint32_t)e[4] | (uint32_t)e[5] | (uint32_t)e[6] | (uint32_t)e[7];
+        if (ballot(act) & ballot(flags >= kDeltaLimit)) {  // uniform
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dl[k] &= kDeltaLimit - 1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const bool f = act && k < rem && ((uint32_t)e[2 * k] >> 31);
@@ -344,6 +522,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                 vpos += (uint32_t)__popcll(mk);
             }
         }
+        src.consumed(pos);
         const int nreal = act ? min(rem, 4) : 0;
         uint32_t cols[4];
         int32_t rowk[4];
@@ -379,6 +558,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         }
         g += 4;
     }
+    cur.pos = pos;
+    cur.dpos = dpos;
+    cur.vpos = vpos;
     if (!live) return;
     if (LAYOUT == 1) {
         if (l < a.m) sink.finish_row(row, kComplete);
@@ -395,6 +577,16 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         }
         if (first && row < a.m) sink.finish_row(row, row_beg < g0 ? kHead : kTail);
     }
+}
+
+// one encoded wave read straight from device memory
+template <int LAYOUT, typename VT, class Sink>
+__device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint64_t *tab,
+                                                    const VT *tval, int64_t slice, uint32_t lane,
+                                                    const typename Sink::Params &sp) {
+    GlobalWords src{(const char *)(a.words + a.woff[slice])};
+    Cursor<VT> cur{0, 0, 0, a.escd + a.doff[slice], (const VT *)a.escv + a.voff[slice]};
+    decode_slice<LAYOUT, VT, Sink>(a, tab, tval, slice, lane, sp, src, cur);
 }
 
 template <typename VT>
@@ -430,23 +622,93 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const int64_t s_end = (xcd_first + xcd_blocks) * wpb * a.num_waves / total;
     const int64_t stride = xcd_blocks * wpb;
     const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    for (int64_t s = s0; s < s_end; s += stride) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
+    for (int64_t s = s0; s < s_end; s += stride)
+        decode_slice_global<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
+}
+
+// Same work as decode_kernel, with every wavefront owning one contiguous run
+// of encoded waves (so that its streams are adjacent in memory) and reading
+// them through an LDS ring (RingWords).  The XCD shares are those of
+// decode_kernel; inside a share the runs are consecutive, which keeps the
+// rows an XCD works on within a window of its share.
+template <int LAYOUT, typename VT, class Sink, int MINW>
+__global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sink::Params sp) {
+    __shared__ uint64_t s_tab[kSlots];
+    __shared__ VT s_val[kSlots];
+    extern __shared__ uint32_t s_ring[];  // kRingWords per wavefront
+    stage_tables<VT>(a, s_tab, s_val);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const int64_t wpb = blockDim.x / kWave;
+    const int64_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t G = gridDim.x, xcd = blockIdx.x % kNumXcd, pos_in_xcd = blockIdx.x / kNumXcd;
+    const int64_t q = G / kNumXcd, rr = G % kNumXcd;
+    const int64_t xcd_blocks = q + (xcd < rr ? 1 : 0);
+    const int64_t xcd_first = xcd * q + (xcd < rr ? xcd : rr);
+    const int64_t total = G * wpb;
+    const int64_t s_begin = xcd_first * wpb * a.num_waves / total;
+    const int64_t s_end = (xcd_first + xcd_blocks) * wpb * a.num_waves / total;
+    const int64_t nw = xcd_blocks * wpb, widx = pos_in_xcd * wpb + wib;
+    const int64_t sa = s_begin + widx * (s_end - s_begin) / nw;
+    const int64_t sb = s_begin + (widx + 1) * (s_end - s_begin) / nw;
+    if (sa >= sb) return;
+    RingWords<kRingWords> src;
+    const uint64_t w0 = a.woff[sa];
+    src.start(s_ring + wib * kRingWords, a.words + w0, (uint32_t)(4 * (a.woff[sb] - w0)), lane);
+    Cursor<VT> cur{0, 0, 0, a.escd + a.doff[sa], (const VT *)a.escv + a.voff[sa]};
+    for (int64_t s = sa; s < sb; ++s) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp, src, cur);
 }
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
-// heads of the following lanes) + beta * y
+// heads of the following lanes) + beta * y.  One thread per split row sums a
+// short one (at most kLongSplit following lanes) by itself; a long one (a
+// power-law row can span thousands of lanes) is summed by the whole
+// wavefront, lanes striding over its partials, then a butterfly reduction.
+constexpr int kLongSplit = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 template <typename VT>
-__global__ void fixup_kernel(const int32_t *split_row, const int32_t *first, const int32_t *last,
-                             int64_t nsplit, const double *partial, int KC, VT *Y, int64_t ldy,
-                             double alpha, double beta) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsplit * KC) return;
-    const int64_t s = i / KC, c = i % KC;
-    const int64_t a = first[s], b = last[s];
-    double sum = partial[(2 * a + 1) * KC + c];
-    for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
-    VT *y = Y + (int64_t)split_row[s] * ldy + c;
-    *y = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*y);
+__global__ __launch_bounds__(256) void fixup_kernel(const int32_t *split_row, const int32_t *first,
+                                                    const int32_t *last, int64_t nsplit,
+                                                    const double *partial, int KC, VT *Y,
+                                                    int64_t ldy, double alpha, double beta) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const bool valid = s < nsplit;
+    int32_t a = 0, b = 0, row = 0;
+    if (valid) {
+        a = first[s];
+        b = last[s];
+        row = split_row[s];
+    }
+    const bool longrow = valid && b - a > kLongSplit;
+    auto put = [&](int32_t r, int c, double sum) {
+        VT *y = Y + (int64_t)r * ldy + c;
+        *y = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*y);
+    };
+    if (valid && !longrow) {
+        for (int c = 0; c < KC; ++c) {
+            double sum = partial[(2 * (int64_t)a + 1) * KC + c];
+            for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
+            put(row, c, sum);
+        }
+    }
+    uint64_t lm = ballot(longrow);
+    while (lm) {  // wave-uniform
+        const int src = __builtin_ctzll(lm);
+        lm &= lm - 1;
+        const int32_t la = __shfl(a, src), lb = __shfl(b, src), lr = __shfl(row, src);
+        for (int c = 0; c < KC; ++c) {
+            double sum = lane == 0 ? partial[(2 * (int64_t)la + 1) * KC + c] : 0.0;
+            for (int64_t l = (int64_t)la + 1 + lane; l <= lb; l += kWave) sum += partial[(2 * l) * KC + c];
+            sum = wave_sum(sum);
+            if (lane == 0) put(lr, c, sum);
+        }
+    }
 }
 
 // Y[rows, :KC] = beta * Y (beta == 0: zero)
@@ -499,7 +761,8 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         sp.alpha = alpha;
         sp.beta = beta;
         for (int w = wib; w < task.num_waves; w += wpb)
-            decode_slice<1, VT, SpmmSink<VT, 1, true>>(a, s_tab, s_val, task.first_wave + w, lane, sp);
+            decode_slice_global<1, VT, SpmmSink<VT, 1, true>>(a, s_tab, s_val, task.first_wave + w,
+                                                              lane, sp);
     }
 }
 
@@ -718,15 +981,42 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (a.layout == 2 && a.nsplit > 0) {
-            const int64_t tot = a.nsplit * KC;
-            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256), 0,
                                st, a.split_row, a.split_first, a.split_last, a.nsplit, partial, KC,
                                Y + c0, ldy, alpha, beta);
             e = hipGetLastError();
         }
         return e;
     };
-    if (k == 1 && ldx == 1 && ldy == 1) return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
+    if (k == 1 && ldx == 1 && ldy == 1 && a.n * (int64_t)sizeof(VT) <= (1ll << 32)) {
+        if (L.ring && a.layout == 1) {
+            typedef SpmmSink<VT, 1, true, double, true> SinkT;
+            typename SinkT::Params sp;
+            sp.X = X;
+            sp.ldx = 1;
+            sp.Y = Y;
+            sp.ldy = 1;
+            sp.partial = partial;
+            sp.alpha = alpha;
+            sp.beta = beta;
+            auto kern = ring_kernel<1, VT, SinkT, 4>;
+            const size_t lds = (size_t)L.waves_per_wg * kRingWords * 4;
+            int per_cu = L.wg_per_cu;
+            if (per_cu <= 0) {
+                hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)block.x, lds);
+                if (e != hipSuccess) return e;
+                per_cu = per_cu > 0 ? per_cu : 1;
+            }
+            const int64_t need = (a.num_waves + L.waves_per_wg - 1) / L.waves_per_wg;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
+            hipLaunchKernelGGL(kern, dim3(grid), block, lds, st, a, sp);
+            return hipGetLastError();
+        }
+        return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
+    }
     // widest column chunk that fits the registers without spilling
     const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
     const int kcmax = std::is_same<VT, double>::value ? 8 : 16;
@@ -807,8 +1097,7 @@ hipError_t csr_impl(const CsrDev &c, int k, const VT *X, int64_t ldx, VT *Y, int
                                dim3(256), 0, st, c, X + c0, ldx, Y + c0, ldy, alpha, beta, partial);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess || c.nsplit == 0) return e;
-            const int64_t tot = c.nsplit * KC;
-            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((c.nsplit + 255) / 256)), dim3(256), 0,
                                st, c.split_row, c.split_first, c.split_last, c.nsplit, partial, KC,
                                Y + c0, ldy, alpha, beta);
             return hipGetLastError();

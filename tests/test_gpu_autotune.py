@@ -44,7 +44,7 @@ def test_autotune_band_and_cache(tmp_path):
     assert opts in cands
     _check(opts, rp, ci, v, 200_000, torch)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("dtans-autotune-v1 ")
+    assert len(lines) == 1 and lines[0].startswith("dtans-autotune-v2 ")
     # a repeated search is answered from the cache
     t0 = time.time()
     opts2, ms2 = P.autotune(rp, ci, v, 200_000, budget_s=6.0, cache=cache)

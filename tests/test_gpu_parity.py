@@ -116,6 +116,30 @@ def test_spmv_parity(case, layout, T, dtype):
     assert torch.equal(y, y2)
 
 
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_spmv_stream_stages_agree(case, dtype):
+    """Row layout: the SpMV that stages its streams through an LDS ring and
+    the one that reads them directly give the same y bit for bit (same
+    products in the same order), and both match the oracle."""
+    torch = need_gpu()
+    name, rp, ci, v, n = CASES[case]
+    v = v.astype(dtype)
+    m = len(rp) - 1
+    x = torch.from_numpy(workloads.vector(n, 7, dtype)).cuda()
+    ys = []
+    for stage in (P.STAGE_DIRECT, P.STAGE_RING):
+        progress("spmv stages %s %s stage=%d" % (name, dtype.__name__, stage))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout="row", stream_stage=stage)
+        assert A.info()["stream_stage"] == stage
+        ys.append(A.spmv(x))
+        yn = torch.full((m,), float("nan"), dtype=x.dtype, device="cuda")
+        A.spmv(x, yn, alpha=2.0, beta=0.0)
+        check_spmv(yn.cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 2.0, 0.0, dtype)
+    assert torch.equal(ys[0], ys[1])
+    check_spmv(ys[1].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, dtype)
+
+
 @pytest.mark.parametrize("layout,T", LAYOUTS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("k", [1, 3, 8, 32, 37])
@@ -243,9 +267,13 @@ def test_launch_shapes_agree():
     n = 20 ** 3
     x = torch.from_numpy(workloads.vector(n, 2)).cuda()
     ref = None
-    for wpw, wgcu in ((1, 1), (4, 2), (14, 2), (16, 1), (7, 3)):
-        progress("launch shape %d x %d" % (wpw, wgcu))
-        A = P.Matrix.from_csr(rp, ci, v, n, layout="row", waves_per_wg=wpw, wg_per_cu=wgcu)
+    shapes = [(wpw, wgcu, P.STAGE_DIRECT) for wpw, wgcu in ((1, 1), (4, 2), (14, 2), (16, 1), (7, 3))]
+    shapes += [(16, 0, P.STAGE_RING), (8, 0, P.STAGE_RING), (4, 1, P.STAGE_RING), (1, 2, P.STAGE_RING),
+               (16, 1, P.STAGE_RING)]
+    for wpw, wgcu, stage in shapes:
+        progress("launch shape %d x %d stage %d" % (wpw, wgcu, stage))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout="row", waves_per_wg=wpw, wg_per_cu=wgcu,
+                              stream_stage=stage)
         y = A.spmv(x)
         if ref is None:
             ref = y

@@ -209,31 +209,41 @@ def _auto_resolution(rp, ci, v, n, **kw):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_autotune_candidates_regular(dtype):
-    """A regular many-row matrix: the automatic encoding (row layout) comes
-    first with the launch shape the library picks by itself, the nonzero
-    layout follows with lane lengths around its automatic choice, and every
-    launch shape respects the CU's wave slots and LDS-limited workgroups."""
+    """A regular many-row matrix: the automatic encoding (row layout, LDS-ring
+    SpMV with the library's own launch shape) comes first, direct-read shapes
+    follow, then the nonzero layout with lane lengths around its automatic
+    choice; every direct-read shape respects the CU's wave slots and the
+    LDS-limited workgroups per CU."""
     rp, ci, v = workloads.band(200_000, 8, 32, seed=3)
     v = v.astype(dtype)
     c = P.autotune_candidates(rp, len(ci), dtype)
     assert c[0]["layout"] == P.LAYOUT_ROW and c[0]["lane_nnz"] == 0
+    assert c[0]["stream_stage"] == P.STAGE_RING and c[0]["wg_per_cu"] == 0
     lay, T = _auto_resolution(rp, ci, v, 200_000)
     assert (lay, T) == (c[0]["layout"], c[0]["lane_nnz"])
-    A = P.Matrix.from_csr(rp, ci, v, 200_000)
-    assert A.info()["waves_per_wg"] == c[0]["waves_per_wg"]
+    info = P.Matrix.from_csr(rp, ci, v, 200_000).info()
+    assert info["waves_per_wg"] == c[0]["waves_per_wg"]
+    assert info["stream_stage"] == P.STAGE_RING
     maxwg = 2 if dtype == np.float64 else 3
-    assert c[0]["wg_per_cu"] == maxwg
-    keys = [(o["layout"], o["lane_nnz"], o["waves_per_wg"], o["wg_per_cu"]) for o in c]
+    keys = [tuple(o.values()) for o in c]
     assert len(set(keys)) == len(keys)
     Ts = sorted({o["lane_nnz"] for o in c if o["layout"] == P.LAYOUT_NNZ})
     assert len(Ts) >= 2 and all(t % 4 == 0 and 32 <= t <= 512 for t in Ts)
+    assert {o["stream_stage"] for o in c if o["layout"] == P.LAYOUT_ROW} == {
+        P.STAGE_RING, P.STAGE_DIRECT}
     for o in c:
+        if o["stream_stage"] == P.STAGE_RING:
+            assert o["layout"] == P.LAYOUT_ROW and o["waves_per_wg"] in (4, 8, 16)
+            continue
         slots = 32 if o["layout"] == P.LAYOUT_ROW else 28
         assert 1 <= o["wg_per_cu"] <= maxwg
         assert 2 <= o["waves_per_wg"] <= min(16, slots // o["wg_per_cu"])
     # encodings are grouped: each (layout, lane_nnz) appears in one run
     runs = [k[:2] for i, k in enumerate(keys) if i == 0 or keys[i - 1][:2] != k[:2]]
     assert len(runs) == len(set(runs))
+    # a fixed stage is kept
+    c = P.autotune_candidates(rp, len(ci), dtype, layout="row", stream_stage=P.STAGE_DIRECT)
+    assert c and all(o["stream_stage"] == P.STAGE_DIRECT for o in c)
 
 
 def test_autotune_candidates_small_and_fixed():
@@ -247,7 +257,8 @@ def test_autotune_candidates_small_and_fixed():
     c = P.autotune_candidates(rp, len(ci), layout="row", waves_per_wg=4)
     assert c and all(o["layout"] == P.LAYOUT_ROW and o["waves_per_wg"] == 4 for o in c)
     c = P.autotune_candidates(rp, len(ci), layout="nnz", lane_nnz=64, waves_per_wg=8, wg_per_cu=2)
-    assert c == [{"layout": P.LAYOUT_NNZ, "lane_nnz": 64, "waves_per_wg": 8, "wg_per_cu": 2}]
+    assert c == [{"layout": P.LAYOUT_NNZ, "lane_nnz": 64, "waves_per_wg": 8, "wg_per_cu": 2,
+                  "stream_stage": 0}]
     # empty matrix: one encoding, still valid shapes
     c = P.autotune_candidates(np.zeros(1, np.int32), 0)
     assert c and c[0]["layout"] == P.LAYOUT_NNZ
@@ -263,6 +274,8 @@ def test_autotune_candidates_errors():
         P.autotune_candidates(rp, len(ci), k=0)
     with pytest.raises(P.DtansError):
         P.autotune_candidates(rp, len(ci), waves_per_wg=17)
+    with pytest.raises(P.DtansError):
+        P.autotune_candidates(rp, len(ci), stream_stage=3)
     bad = rp.copy()
     bad[10] = bad[11] + 1
     with pytest.raises(P.DtansError):
