@@ -143,7 +143,7 @@ def main():
     ap.add_argument("--waves-per-wg", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--stream-stage", type=int, default=0,
-                    help="row-layout SpMV: 0 auto, 1 direct word reads, 2 LDS ring")
+                    help="SpMV: 0 auto, 1 direct word reads, 2 LDS ring")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -61,7 +61,7 @@ typedef enum { DTANS_F32 = 1, DTANS_F64 = 2 } dtans_dtype;
  * summed by a fix-up pass.  AUTO lets the encoder choose. */
 typedef enum { DTANS_LAYOUT_AUTO = 0, DTANS_LAYOUT_ROW = 1, DTANS_LAYOUT_NNZ = 2 } dtans_layout;
 
-/* How the row-layout SpMV reads its word streams (dtans_encode_opts). */
+/* How SpMV (one right-hand side) reads its word streams (dtans_encode_opts). */
 enum { DTANS_STAGE_AUTO = 0, DTANS_STAGE_DIRECT = 1, DTANS_STAGE_RING = 2 };
 
 typedef struct {
@@ -70,8 +70,8 @@ typedef struct {
     int32_t waves_per_wg;  /* kernel launch: wavefronts per workgroup (1..16); 0 = auto */
     int32_t wg_per_cu;     /* kernel launch: persistent workgroups per CU; 0 = auto */
     int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
-    int32_t stream_stage;  /* ROW layout SpMV: 0 = auto, 1 = read stream words directly
-                              from device memory, 2 = stage them through an LDS ring */
+    int32_t stream_stage;  /* SpMV: 0 = auto, 1 = read stream words directly from
+                              device memory, 2 = stage them through an LDS ring */
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -205,10 +205,10 @@ void dtans_csr_destroy(dtans_csr *csr);
  * Autotuner (encode-time parameters; no equivalent in the paper, which uses
  * one fixed launch per GPU).  Candidate options are the fields of *in left at
  * 0 / AUTO, searched over: layout {ROW, NNZ}; for NNZ, nonzeros per lane
- * around the automatic choice (multiples of 4 between 32 and 512); for ROW,
- * the stream stage (LDS ring with 16, 8 or 4 waves per workgroup and as many
- * workgroups per CU as fit, then direct reads); and launch shapes of the
- * direct-read kernels (workgroups per CU up to the LDS limit, waves per
+ * around the automatic choice (multiples of 4 between 32 and 512); for SpMV
+ * (k = 1), the stream stage (LDS ring with 16, 8 or 4 waves per workgroup and
+ * as many workgroups per CU as fit, then direct reads); and launch shapes of
+ * the direct-read kernels (workgroups per CU up to the LDS limit, waves per
  * workgroup filling the CU's wave slots, then half and a quarter of that).
  * Fields set in *in are kept in every candidate.
  *

@@ -69,10 +69,11 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // columns in the nonzero-balanced layout, where a lane sums a bounded number
 // of nonzeros (at most 1024; measured error ~1e-7 of |A||x| at 512) before
 // its partial sums are combined in double.
-// DEFER (lanes holding single rows, KC <= 4): a segment's x values are
-// loaded when it arrives and multiplied when the next segment arrives or the
-// row ends, so their latency overlaps one decoding step.
-template <typename VT, int KC, bool UNIT, typename ACC = double, bool DEFER = false>
+// DEFER (KC <= 4): a segment's x values are loaded when it arrives and
+// multiplied at the start of the next decoding step (or when the lane ends),
+// so their latency overlaps one step.  1: lanes hold single rows; 2: lanes
+// may cross rows, and the rows of the deferred nonzeros are kept with them.
+template <typename VT, int KC, bool UNIT, typename ACC = double, int DEFER = 0>
 struct SpmmSink {
     static_assert(!DEFER || KC <= 4, "deferred products keep 4*KC x values in registers");
     static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
@@ -89,6 +90,7 @@ struct SpmmSink {
     int32_t cur, head_row;  // row being accumulated; the lane's head row or -1
     ACC acc[KC];
     VT pv[DEFER ? 4 : 1], px[DEFER ? 4 : 1][KC];  // deferred segment
+    int32_t prow[DEFER == 2 ? 4 : 1];             // its rows (DEFER 2)
     int pn;                                       // its nonzeros (0: none)
     // cur starts at -1: a row is finished only after the sink has seen one of
     // its nonzeros (empty rows are written by the decoder via empty_row)
@@ -99,7 +101,7 @@ struct SpmmSink {
     }
     // multiply the deferred segment (its x loads were issued a step ago)
     __device__ __forceinline__ void consume() {
-        if constexpr (DEFER) {
+        if constexpr (DEFER == 1) {
             if (!ballot(pn < 4)) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -112,6 +114,26 @@ struct SpmmSink {
                     for (int c = 0; c < KC; ++c) {
                         const ACC t = fma((ACC)pv[k], (ACC)px[k][c], acc[c]);
                         acc[c] = k < pn ? t : acc[c];
+                    }
+            }
+            pn = 0;
+        } else if constexpr (DEFER == 2) {
+            // rows never decrease along a lane: prow[3] == cur means no row ends
+            if (!ballot(pn < 4 || prow[3] != cur)) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)pv[k], (ACC)px[k][c], acc[c]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < pn) {
+                        if (prow[k] != cur) {
+                            if (cur >= 0) store(cur, cur == head_row ? kHead : kComplete);
+                            cur = prow[k];
+                        }
+#pragma unroll
+                        for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)pv[k], (ACC)px[k][c], acc[c]);
                     }
             }
             pn = 0;
@@ -144,7 +166,8 @@ struct SpmmSink {
     __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
                                             int64_t, const int32_t rowk[4]) {
         if constexpr (DEFER) {
-            if constexpr (!MULTI) {
+            static_assert(MULTI == (DEFER == 2), "DEFER 1 is for single-row lanes, 2 for the others");
+            {
                 // every lane loads four x values (column 0 stands in for
                 // nonzeros past the lane's end; their products are dropped)
                 uint32_t cc[4];
@@ -160,10 +183,13 @@ struct SpmmSink {
                     for (int c = 0; c < KC; ++c) px[k][c] = xrow(cc[k])[c];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) pv[k] = v[k];
+                if constexpr (DEFER == 2) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) prow[k] = rowk[k];
+                }
                 pn = nreal;
                 return;
             }
-            consume();
         }
         if (KC <= 4) {
             VT x[4][KC];
@@ -303,8 +329,9 @@ struct DecodeSink {
 // previous step's ballots, so each step waits for one memory round trip.
 struct GlobalWords {
     const char *W;  // stream base of the current encoded wave
-    __device__ __forceinline__ uint32_t word(uint32_t off) const {
-        return *(const uint32_t *)(W + off);
+    // the word at byte offset pos (uniform) + 4 * (lanes of mask below this one)
+    __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
+        return *(const uint32_t *)(W + pos + 4 * lane_prefix(mask));
     }
     __device__ __forceinline__ void step_begin() {}
     __device__ __forceinline__ void consumed(uint32_t) {}
@@ -326,8 +353,14 @@ struct GlobalWords {
 template <int kRing>
 struct RingWords {
     static constexpr uint32_t kChunk = 1024;
+    // the first kMirror words of the ring are kept a second time after its
+    // end, so that the at most 64 words one read instruction spans never
+    // wrap: a read is a prefix count from a uniform start, as from memory
+    static constexpr int kMirror = 64;
+    static constexpr int kWords = kRing + kMirror;  // LDS words per wavefront
     static_assert(kRing * 4 >= (int)kChunk + 3 * 768, "ring too small for two steps of lead");
-    uint32_t *ring;     // this wavefront's ring (kRing words)
+    static_assert((kRing & (kRing - 1)) == 0 && kRing % 256 == 0, "ring of whole chunks");
+    uint32_t *ring;     // this wavefront's ring (kWords words)
     const char *base;   // the run's first word rounded down to 16 bytes
     uint32_t skew;      // bytes from base to the run's first word (0..12)
     uint32_t total;     // skew + bytes in the run
@@ -346,7 +379,9 @@ struct RingWords {
         return *(const uint4 *)(base + (o < total ? o : 0u));
     }
     __device__ __forceinline__ void write_chunk_part(uint32_t at, uint4 v) {
-        *(uint4 *)(ring + (((at >> 2) + 4 * lane) & (kRing - 1))) = v;
+        const uint32_t i = ((at >> 2) + 4 * lane) & (kRing - 1);
+        *(uint4 *)(ring + i) = v;
+        if (i < kMirror) *(uint4 *)(ring + kRing + i) = v;
     }
     __device__ __forceinline__ void start(uint32_t *r, const uint32_t *first, uint32_t bytes,
                                           uint32_t ln) {
@@ -366,9 +401,11 @@ struct RingWords {
             }
         }
     }
-    // off: bytes from the run's first word
-    __device__ __forceinline__ uint32_t word(uint32_t off) const {
-        return ring[((off + skew) >> 2) & (kRing - 1)];
+    // pos: bytes from the run's first word (uniform, so the start address is
+    // scalar work); the lane adds its prefix count
+    __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
+        const uint32_t *at = ring + (((pos + skew) >> 2) & (kRing - 1));
+        return at[lane_prefix(mask)];
     }
     __device__ __forceinline__ void step_begin() {
         if (has_pend) {
@@ -398,33 +435,57 @@ struct Cursor {
     const VT *EV;
 };
 
+// Where a lane's stream sits in the matrix: its first nonzero g0 and count;
+// its first row with that row's [beg, end) and the end of the row after it
+// (layout NNZ).  The nonzero layout needs two dependent loads (lane_row, then
+// row_ptr), so callers may issue the first a wave ahead (lane_first_row).
+struct LaneGeo {
+    int64_t g0;
+    int cnt;
+    int32_t row, row_beg, row_end, next_end;
+};
+
+template <int LAYOUT>
+__device__ __forceinline__ int32_t lane_first_row(const DevMat &a, int64_t slice, uint32_t lane) {
+    const int64_t l = slice * kWave + lane;
+    if (l >= a.num_lanes) return 0;
+    return LAYOUT == 1 ? (int32_t)l : a.lane_row[l];
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint32_t lane,
+                                            int32_t first_row) {
+    LaneGeo q{0, 0, 0, 0, 0, 0};
+    const int64_t l = slice * kWave + lane;
+    if (l < a.num_lanes) {
+        q.row = first_row;
+        if (LAYOUT == 1) {
+            q.row_beg = a.row_ptr[l];
+            q.cnt = a.row_ptr[l + 1] - q.row_beg;
+            q.g0 = q.row_beg;
+        } else {
+            q.g0 = l * (int64_t)a.lane_nnz;
+            q.cnt = (int)min((int64_t)a.lane_nnz, a.nnz - q.g0);
+            q.row_beg = a.row_ptr[first_row];
+            q.row_end = a.row_ptr[first_row + 1];
+            q.next_end = first_row + 2 <= a.m ? a.row_ptr[first_row + 2] : (int32_t)a.nnz;
+        }
+    }
+    return q;
+}
+
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
 // nonzeros of this thread's lane to a sink constructed here.
 template <int LAYOUT, typename VT, class Sink, class Src>
 __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
                                              const VT *__restrict__ tval, int64_t slice,
                                              uint32_t lane, const typename Sink::Params &sp,
-                                             Src &src, Cursor<VT> &cur) {
+                                             Src &src, Cursor<VT> &cur, const LaneGeo &geo) {
     const int64_t l = slice * kWave + lane;
     const bool live = l < a.num_lanes;
-    int64_t g0 = 0;
-    int cnt = 0;
-    int32_t row = 0, row_beg = 0, row_end = 0, next_end = 0;
-    if (live) {
-        if (LAYOUT == 1) {
-            row = (int32_t)l;
-            row_beg = a.row_ptr[l];
-            cnt = a.row_ptr[l + 1] - row_beg;
-            g0 = row_beg;
-        } else {
-            g0 = l * (int64_t)a.lane_nnz;
-            cnt = (int)min((int64_t)a.lane_nnz, a.nnz - g0);
-            row = a.lane_row[l];
-            row_beg = a.row_ptr[row];
-            row_end = a.row_ptr[row + 1];
-            next_end = row + 2 <= a.m ? a.row_ptr[row + 2] : (int32_t)a.nnz;
-        }
-    }
+    const int64_t g0 = geo.g0;
+    const int cnt = geo.cnt;
+    int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, next_end = geo.next_end;
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
     const int S = (cnt + 3) >> 2;
     const int Smax = __builtin_amdgcn_readfirstlane(wave_max(S));  // uniform: scalar loop
@@ -434,15 +495,14 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     uint32_t pos = cur.pos, dpos = cur.dpos, vpos = cur.vpos;
     const uint32_t *__restrict__ ED = cur.ED;
     const VT *__restrict__ EV = cur.EV;
-    auto word = [&](uint32_t byte_off) { return src.word(byte_off); };
     uint32_t w1, w2, w3;
     {
         // lanes without a stream read a neighbouring word (buffers are padded)
         const uint64_t mk = ballot(S > 0);
-        const uint32_t pre = 4 * lane_prefix(mk), c = 4 * (uint32_t)__popcll(mk);
-        w1 = word(pos + pre);
-        w2 = word(pos + c + pre);
-        w3 = word(pos + 2 * c + pre);
+        const uint32_t c = 4 * (uint32_t)__popcll(mk);
+        w1 = src.read(pos, mk);
+        w2 = src.read(pos + c, mk);
+        w3 = src.read(pos + 2 * c, mk);
         pos += 3 * c;
         src.step_begin();
         src.consumed(pos);
@@ -479,9 +539,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             const uint64_t m1 = m3 & ~ballot(ext1);
             const uint64_t m2 = m3 & ~ballot(ext2);
             const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
-            const uint32_t l1 = word(pos + 4 * lane_prefix(m1));
-            const uint32_t l2 = word(pos + c1 + 4 * lane_prefix(m2));
-            const uint32_t l3 = word(pos + c1 + c2 + 4 * lane_prefix(m3));
+            const uint32_t l1 = src.read(pos, m1);
+            const uint32_t l2 = src.read(pos + c1, m2);
+            const uint32_t l3 = src.read(pos + c1 + c2, m3);
             pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
             w1 = ext1 ? x1 : l1;
             w2 = ext2 ? x2 : l2;
@@ -526,7 +586,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         const int nreal = act ? min(rem, 4) : 0;
         uint32_t cols[4];
         int32_t rowk[4];
-        if (LAYOUT == 1) {
+        if constexpr (LAYOUT == 1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 col += dl[k];
@@ -586,7 +646,8 @@ __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint6
                                                     const typename Sink::Params &sp) {
     GlobalWords src{(const char *)(a.words + a.woff[slice])};
     Cursor<VT> cur{0, 0, 0, a.escd + a.doff[slice], (const VT *)a.escv + a.voff[slice]};
-    decode_slice<LAYOUT, VT, Sink>(a, tab, tval, slice, lane, sp, src, cur);
+    const LaneGeo geo = lane_geo<LAYOUT>(a, slice, lane, lane_first_row<LAYOUT>(a, slice, lane));
+    decode_slice<LAYOUT, VT, Sink>(a, tab, tval, slice, lane, sp, src, cur, geo);
 }
 
 template <typename VT>
@@ -635,7 +696,7 @@ template <int LAYOUT, typename VT, class Sink, int MINW>
 __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
-    extern __shared__ uint32_t s_ring[];  // kRingWords per wavefront
+    extern __shared__ uint32_t s_ring[];  // RingWords<kRingWords>::kWords per wavefront
     stage_tables<VT>(a, s_tab, s_val);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
@@ -653,9 +714,21 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
     if (sa >= sb) return;
     RingWords<kRingWords> src;
     const uint64_t w0 = a.woff[sa];
-    src.start(s_ring + wib * kRingWords, a.words + w0, (uint32_t)(4 * (a.woff[sb] - w0)), lane);
+    src.start(s_ring + wib * RingWords<kRingWords>::kWords, a.words + w0,
+              (uint32_t)(4 * (a.woff[sb] - w0)), lane);
     Cursor<VT> cur{0, 0, 0, a.escd + a.doff[sa], (const VT *)a.escv + a.voff[sa]};
-    for (int64_t s = sa; s < sb; ++s) decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp, src, cur);
+    // lane geometry two stages ahead: first rows of wave s + 2 and row
+    // pointers of wave s + 1 are loaded while wave s decodes
+    LaneGeo geo = lane_geo<LAYOUT>(a, sa, lane, lane_first_row<LAYOUT>(a, sa, lane));
+    int32_t fr1 = sa + 1 < sb ? lane_first_row<LAYOUT>(a, sa + 1, lane) : 0;
+    for (int64_t s = sa; s < sb; ++s) {
+        const int32_t fr2 = s + 2 < sb ? lane_first_row<LAYOUT>(a, s + 2, lane) : 0;
+        LaneGeo next{0, 0, 0, 0, 0, 0};
+        if (s + 1 < sb) next = lane_geo<LAYOUT>(a, s + 1, lane, fr1);
+        decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        geo = next;
+        fr1 = fr2;
+    }
 }
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
@@ -989,31 +1062,42 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         return e;
     };
     if (k == 1 && ldx == 1 && ldy == 1 && a.n * (int64_t)sizeof(VT) <= (1ll << 32)) {
-        if (L.ring && a.layout == 1) {
-            typedef SpmmSink<VT, 1, true, double, true> SinkT;
-            typename SinkT::Params sp;
-            sp.X = X;
-            sp.ldx = 1;
-            sp.Y = Y;
-            sp.ldy = 1;
-            sp.partial = partial;
-            sp.alpha = alpha;
-            sp.beta = beta;
-            auto kern = ring_kernel<1, VT, SinkT, 4>;
-            const size_t lds = (size_t)L.waves_per_wg * kRingWords * 4;
-            int per_cu = L.wg_per_cu;
-            if (per_cu <= 0) {
-                hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                if (e != hipSuccess) return e;
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)block.x, lds);
-                if (e != hipSuccess) return e;
-                per_cu = per_cu > 0 ? per_cu : 1;
-            }
-            const int64_t need = (a.num_waves + L.waves_per_wg - 1) / L.waves_per_wg;
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
-            hipLaunchKernelGGL(kern, dim3(grid), block, lds, st, a, sp);
-            return hipGetLastError();
+        if (L.ring) {
+            auto ring = [&](auto sinkc, auto kern) -> hipError_t {
+                typedef typename decltype(sinkc)::type SinkT;
+                typename SinkT::Params sp;
+                sp.X = X;
+                sp.ldx = 1;
+                sp.Y = Y;
+                sp.ldy = 1;
+                sp.partial = partial;
+                sp.alpha = alpha;
+                sp.beta = beta;
+                const size_t lds = (size_t)L.waves_per_wg * RingWords<kRingWords>::kWords * 4;
+                int per_cu = L.wg_per_cu;
+                if (per_cu <= 0) {
+                    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                    if (e != hipSuccess) return e;
+                    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)block.x, lds);
+                    if (e != hipSuccess) return e;
+                    per_cu = per_cu > 0 ? per_cu : 1;
+                }
+                const int64_t need = (a.num_waves + L.waves_per_wg - 1) / L.waves_per_wg;
+                const int grid =
+                    (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
+                hipLaunchKernelGGL(kern, dim3(grid), block, lds, st, a, sp);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess || a.layout != 2 || a.nsplit == 0) return e;
+                hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256),
+                                   0, st, a.split_row, a.split_first, a.split_last, a.nsplit, partial,
+                                   1, Y, ldy, alpha, beta);
+                return hipGetLastError();
+            };
+            typedef SpmmSink<VT, 1, true, double, 1> RowSink;
+            typedef SpmmSink<VT, 1, true, double, 2> NnzSink;
+            if (a.layout == 1) return ring(TypeBox<RowSink>(), ring_kernel<1, VT, RowSink, 4>);
+            return ring(TypeBox<NnzSink>(), ring_kernel<2, VT, NnzSink, 4>);
         }
         return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
     }

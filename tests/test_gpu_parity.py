@@ -117,11 +117,12 @@ def test_spmv_parity(case, layout, T, dtype):
 
 
 @pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layout,T", LAYOUTS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_spmv_stream_stages_agree(case, dtype):
-    """Row layout: the SpMV that stages its streams through an LDS ring and
-    the one that reads them directly give the same y bit for bit (same
-    products in the same order), and both match the oracle."""
+def test_spmv_stream_stages_agree(case, layout, T, dtype):
+    """The SpMV that stages its streams through an LDS ring and the one that
+    reads them directly give the same y bit for bit (same products in the
+    same order), and both match the oracle."""
     torch = need_gpu()
     name, rp, ci, v, n = CASES[case]
     v = v.astype(dtype)
@@ -129,8 +130,8 @@ def test_spmv_stream_stages_agree(case, dtype):
     x = torch.from_numpy(workloads.vector(n, 7, dtype)).cuda()
     ys = []
     for stage in (P.STAGE_DIRECT, P.STAGE_RING):
-        progress("spmv stages %s %s stage=%d" % (name, dtype.__name__, stage))
-        A = P.Matrix.from_csr(rp, ci, v, n, layout="row", stream_stage=stage)
+        progress("spmv stages %s %s T=%d %s stage=%d" % (name, layout, T, dtype.__name__, stage))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T, stream_stage=stage)
         assert A.info()["stream_stage"] == stage
         ys.append(A.spmv(x))
         yn = torch.full((m,), float("nan"), dtype=x.dtype, device="cuda")

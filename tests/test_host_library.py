@@ -229,11 +229,11 @@ def test_autotune_candidates_regular(dtype):
     assert len(set(keys)) == len(keys)
     Ts = sorted({o["lane_nnz"] for o in c if o["layout"] == P.LAYOUT_NNZ})
     assert len(Ts) >= 2 and all(t % 4 == 0 and 32 <= t <= 512 for t in Ts)
-    assert {o["stream_stage"] for o in c if o["layout"] == P.LAYOUT_ROW} == {
-        P.STAGE_RING, P.STAGE_DIRECT}
+    for lay in (P.LAYOUT_ROW, P.LAYOUT_NNZ):
+        assert {o["stream_stage"] for o in c if o["layout"] == lay} == {P.STAGE_RING, P.STAGE_DIRECT}
     for o in c:
         if o["stream_stage"] == P.STAGE_RING:
-            assert o["layout"] == P.LAYOUT_ROW and o["waves_per_wg"] in (4, 8, 16)
+            assert o["waves_per_wg"] in (4, 8, 16) and o["wg_per_cu"] == 0
             continue
         slots = 32 if o["layout"] == P.LAYOUT_ROW else 28
         assert 1 <= o["wg_per_cu"] <= maxwg
@@ -256,9 +256,13 @@ def test_autotune_candidates_small_and_fixed():
     assert c and all(o["layout"] == P.LAYOUT_NNZ and o["wg_per_cu"] == 1 for o in c)
     c = P.autotune_candidates(rp, len(ci), layout="row", waves_per_wg=4)
     assert c and all(o["layout"] == P.LAYOUT_ROW and o["waves_per_wg"] == 4 for o in c)
-    c = P.autotune_candidates(rp, len(ci), layout="nnz", lane_nnz=64, waves_per_wg=8, wg_per_cu=2)
+    c = P.autotune_candidates(rp, len(ci), layout="nnz", lane_nnz=64, waves_per_wg=8, wg_per_cu=2,
+                              stream_stage=P.STAGE_DIRECT)
     assert c == [{"layout": P.LAYOUT_NNZ, "lane_nnz": 64, "waves_per_wg": 8, "wg_per_cu": 2,
-                  "stream_stage": 0}]
+                  "stream_stage": P.STAGE_DIRECT}]
+    # several right-hand sides: no ring candidates
+    c = P.autotune_candidates(rp, len(ci), k=8)
+    assert c and all(o["stream_stage"] == 0 for o in c)
     # empty matrix: one encoding, still valid shapes
     c = P.autotune_candidates(np.zeros(1, np.int32), 0)
     assert c and c[0]["layout"] == P.LAYOUT_NNZ
