@@ -70,8 +70,8 @@ typedef struct {
     int32_t waves_per_wg;  /* kernel launch: wavefronts per workgroup (1..16); 0 = auto */
     int32_t wg_per_cu;     /* kernel launch: persistent workgroups per CU; 0 = auto */
     int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
-    int32_t stream_stage;  /* SpMV: 0 = auto, 1 = read stream words directly from
-                              device memory, 2 = stage them through an LDS ring */
+    int32_t stream_stage;  /* SpMV: 0 = auto (direct), 1 = read stream words directly
+                              from device memory, 2 = stage them through an LDS ring */
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -205,11 +205,11 @@ void dtans_csr_destroy(dtans_csr *csr);
  * Autotuner (encode-time parameters; no equivalent in the paper, which uses
  * one fixed launch per GPU).  Candidate options are the fields of *in left at
  * 0 / AUTO, searched over: layout {ROW, NNZ}; for NNZ, nonzeros per lane
- * around the automatic choice (multiples of 4 between 32 and 512); for SpMV
- * (k = 1), the stream stage (LDS ring with 16, 8 or 4 waves per workgroup and
- * as many workgroups per CU as fit, then direct reads); and launch shapes of
- * the direct-read kernels (workgroups per CU up to the LDS limit, waves per
- * workgroup filling the CU's wave slots, then half and a quarter of that).
+ * around the automatic choice (multiples of 4 between 32 and 512); launch
+ * shapes of the direct-read kernels (workgroups per CU up to the LDS limit,
+ * waves per workgroup filling the CU's wave slots, then half and a quarter of
+ * that); and for SpMV (k = 1) the LDS-ring stream stage with 16, 8 or 4 waves
+ * per workgroup and as many workgroups per CU as fit.
  * Fields set in *in are kept in every candidate.
  *
  * dtans_autotune_candidates is host-only: it writes at most `cap` candidates,

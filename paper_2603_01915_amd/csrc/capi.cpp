@@ -115,10 +115,12 @@ struct dtans_csr {
 
 namespace {
 
-// SpMV stages its streams through an LDS ring unless told not to; a
-// wavefront's run of streams is addressed with 32-bit offsets.
+// SpMV stages its streams through an LDS ring only when asked to (measured:
+// the direct-read kernels, at twice the waves per SIMD, are faster on the
+// workloads here); a wavefront's run of streams is addressed with 32-bit
+// offsets.
 bool uses_ring(const dtans_matrix *h) {
-    return h->stage != DTANS_STAGE_DIRECT && 4 * (int64_t)h->c.words.size() < (1ll << 31);
+    return h->stage == DTANS_STAGE_RING && 4 * (int64_t)h->c.words.size() < (1ll << 31);
 }
 
 Launch plan_launch(const dtans_matrix *h) {
@@ -352,18 +354,17 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
             c.stream_stage = stage;
             out.push_back(c);
         };
-        // SpMV: the LDS-ring kernels (their own shapes; workgroups per CU as
-        // many as fit unless fixed) before the direct-read ones; products with
-        // several right-hand sides always read directly
-        const bool ring = k == 1 && o.stream_stage != DTANS_STAGE_DIRECT;
-        if (ring) {
+        // SpMV: the direct-read shapes, then the LDS-ring kernels (their own
+        // shapes; workgroups per CU as many as fit unless fixed); products
+        // with several right-hand sides always read directly
+        if (o.stream_stage != DTANS_STAGE_RING || k > 1)
+            for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu))
+                push(w.first, w.second, k == 1 ? DTANS_STAGE_DIRECT : o.stream_stage);
+        if (k == 1 && o.stream_stage != DTANS_STAGE_DIRECT) {
             if (o.waves_per_wg) push(o.waves_per_wg, o.wg_per_cu, DTANS_STAGE_RING);
             else
                 for (int w : {16, 8, 4}) push(w, o.wg_per_cu, DTANS_STAGE_RING);
         }
-        if (o.stream_stage != DTANS_STAGE_RING || k > 1)
-            for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu))
-                push(w.first, w.second, k == 1 ? DTANS_STAGE_DIRECT : o.stream_stage);
     }
     return DTANS_OK;
 }

@@ -209,22 +209,23 @@ def _auto_resolution(rp, ci, v, n, **kw):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_autotune_candidates_regular(dtype):
-    """A regular many-row matrix: the automatic encoding (row layout, LDS-ring
-    SpMV with the library's own launch shape) comes first, direct-read shapes
-    follow, then the nonzero layout with lane lengths around its automatic
-    choice; every direct-read shape respects the CU's wave slots and the
-    LDS-limited workgroups per CU."""
+    """A regular many-row matrix: the automatic encoding (row layout, direct
+    reads, the library's own launch shape) comes first, the other shapes and
+    the LDS-ring kernels follow, then the nonzero layout with lane lengths
+    around its automatic choice; every direct-read shape respects the CU's
+    wave slots and the LDS-limited workgroups per CU."""
     rp, ci, v = workloads.band(200_000, 8, 32, seed=3)
     v = v.astype(dtype)
     c = P.autotune_candidates(rp, len(ci), dtype)
     assert c[0]["layout"] == P.LAYOUT_ROW and c[0]["lane_nnz"] == 0
-    assert c[0]["stream_stage"] == P.STAGE_RING and c[0]["wg_per_cu"] == 0
+    assert c[0]["stream_stage"] == P.STAGE_DIRECT
     lay, T = _auto_resolution(rp, ci, v, 200_000)
     assert (lay, T) == (c[0]["layout"], c[0]["lane_nnz"])
     info = P.Matrix.from_csr(rp, ci, v, 200_000).info()
     assert info["waves_per_wg"] == c[0]["waves_per_wg"]
-    assert info["stream_stage"] == P.STAGE_RING
+    assert info["stream_stage"] == P.STAGE_DIRECT
     maxwg = 2 if dtype == np.float64 else 3
+    assert c[0]["wg_per_cu"] == maxwg
     keys = [tuple(o.values()) for o in c]
     assert len(set(keys)) == len(keys)
     Ts = sorted({o["lane_nnz"] for o in c if o["layout"] == P.LAYOUT_NNZ})
