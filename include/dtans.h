@@ -72,6 +72,10 @@ typedef struct {
     int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
     int32_t stream_stage;  /* SpMV: 0 = auto (direct), 1 = read stream words directly
                               from device memory, 2 = stage them through an LDS ring */
+    int32_t max_mult;      /* largest number of slots per symbol, 1..256 (Sec. IV-C's
+                              cap M = 256); 0 = 255, which keeps every base within a
+                              byte so that the kernels use it without a correction */
+    int32_t reserved;
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -91,7 +95,7 @@ typedef struct {
     double delta_cross_entropy, value_cross_entropy; /* H(P, P') of the fitted tables (Eq. 2) */
     double bits_per_nnz;                   /* 8 * stream_bytes / nnz */
     int32_t stream_stage;                  /* SpMV word reads: 1 direct, 2 LDS ring */
-    int32_t reserved;
+    int32_t direct_table;                  /* 1: every base <= 255, used without correction */
 } dtans_info;
 
 typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */

@@ -158,7 +158,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
         return DTANS_OK;
     }
     const Container &c = h->c;
-    gpu_table(c, h->gtab, h->gval);
+    const bool direct = gpu_table(c, h->gtab, h->gval);
     nnz_layout_meta(c, h->lane_row, h->split_row, h->split_first, h->split_last);
     const bool f64 = c.dtype == kF64;
     const void *escv_src = c.escv.data();
@@ -208,6 +208,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.nsplit = (int64_t)h->split_row.size();
     v.lane_nnz = (int32_t)c.lane_nnz;
     v.layout = (int32_t)c.layout;
+    v.base_direct = direct ? 1 : 0;
     h->device = dev;
     h->num_cus = device_cus(dev);
     h->uploaded = true;
@@ -435,6 +436,8 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
         return set_err(DTANS_EINVAL, "waves_per_wg must be 0..16 and wg_per_cu 0..32");
     if (o.stream_stage < 0 || o.stream_stage > DTANS_STAGE_RING)
         return set_err(DTANS_EINVAL, "stream_stage must be 0, 1 or 2");
+    if (o.max_mult < 0 || o.max_mult > kMaxBase)
+        return set_err(DTANS_EINVAL, "max_mult must be 0..256");
     const size_t vb = dtype == DTANS_F64 ? 8 : 4;
     std::vector<int32_t> scol;
     std::vector<uint8_t> sval;
@@ -460,6 +463,7 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     }
     EncodeParams p;
     p.seed = o.perm_seed;
+    p.max_mult = o.max_mult ? (uint32_t)o.max_mult : 255u;
     int layout = 0, T = 0;
     auto_encoding(m, nnz, row_ptr, o, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
@@ -552,6 +556,10 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->value_cross_entropy = c.vtab.cross_entropy;
     o->bits_per_nnz = c.nnz ? 8.0 * o->stream_bytes / c.nnz : 0.0;
     o->stream_stage = uses_ring(mat) ? DTANS_STAGE_RING : DTANS_STAGE_DIRECT;
+    o->direct_table = 1;
+    for (int i = 0; i < kSlots; ++i)
+        if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))
+            o->direct_table = 0;
     return DTANS_OK;
 }
 
@@ -886,7 +894,7 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
     for (int64_t w : {m, n, nnz, (int64_t)dtype, (int64_t)k, (int64_t)inout->layout,
                       (int64_t)inout->lane_nnz, (int64_t)inout->waves_per_wg,
                       (int64_t)inout->wg_per_cu, (int64_t)inout->sort_rows,
-                      (int64_t)inout->stream_stage})
+                      (int64_t)inout->stream_stage, (int64_t)inout->max_mult})
         fp.word((uint64_t)w);
     fp.word(inout->perm_seed);
     if (cache_path) {

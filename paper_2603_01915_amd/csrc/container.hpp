@@ -55,6 +55,7 @@ struct Container {
 struct EncodeParams {
     uint32_t layout = kLayoutRow;
     uint32_t lane_nnz = 0;
+    uint32_t max_mult = 255;  // multiplicity cap, at most M = 256
     uint64_t seed = 1;
     int threads = 0;  // 0 = hardware concurrency
 };
@@ -78,6 +79,7 @@ void nnz_layout_meta(const Container &c, std::vector<int32_t> &lane_row,
                      std::vector<int32_t> &split_last);
 
 // GPU table: one 64-bit entry per slot (see dtans_core.hpp) + one value per slot
-void gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values);
+// returns true for "direct" tables (every base at most 255)
+bool gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values);
 
 }  // namespace dtans

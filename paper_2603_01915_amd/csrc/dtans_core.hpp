@@ -26,7 +26,9 @@
 //   bit   31     the delta-table slot holds the escape symbol
 //   bits 32..47  delta slot:  (base - 1) | digit << 8
 //   bits 48..63  value slot:  (base - 1) | digit << 8
-// plus one value (float or double) per slot in a second array.
+// plus one value (float or double) per slot in a second array.  When every
+// base of both tables is at most 255 ("direct" tables) the two metadata
+// fields hold base | digit << 8 instead (unused slots: base 1).
 #pragma once
 
 #include <stdint.h>
@@ -91,6 +93,35 @@ DTANS_HD bool append_and_check(uint32_t &d, uint32_t &r, uint32_t D, uint32_t Rm
                                uint32_t &word) {
     const uint64_t r64 = (uint64_t)r * Rm1 + r;              // r * R, < 2^64
     const uint64_t d64 = (uint64_t)d * Rm1 + ((uint64_t)d + D);  // d * R + D
+    const bool extract = (r64 >> 32) != 0;
+    if (extract) {
+        word = (uint32_t)d64;
+        d = (uint32_t)(d64 >> 32);
+        r = (uint32_t)(r64 >> 32);
+    } else {
+        d = (uint32_t)d64;
+        r = (uint32_t)r64;
+    }
+    return extract;
+}
+
+// The same two steps for tables whose bases are all at most 255 (an encoder
+// multiplicity cap of 255 instead of M = 256): the GPU entry then holds the
+// base itself in the low byte of a slot's metadata (base | digit << 8), so
+// no +1 is needed, and R = product of the bases < 2^32 needs no wrap.
+DTANS_HD void group4_direct(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, uint32_t &D,
+                            uint32_t &R) {
+    const uint32_t b1 = m1 & 0xffu, b2 = m2 & 0xffu, b3 = m3 & 0xffu;
+    const uint32_t b23 = b2 * b3;
+    const uint32_t lo = meta_digit(m2) * b3 + meta_digit(m3);
+    const uint32_t hi = meta_digit(m0) * b1 + meta_digit(m1);
+    D = hi * b23 + lo;
+    R = (m0 & 0xffu) * b1 * b23;
+}
+
+DTANS_HD bool append_direct(uint32_t &d, uint32_t &r, uint32_t D, uint32_t R, uint32_t &word) {
+    const uint64_t r64 = (uint64_t)r * R;
+    const uint64_t d64 = (uint64_t)d * R + D;
     const bool extract = (r64 >> 32) != 0;
     if (extract) {
         word = (uint32_t)d64;

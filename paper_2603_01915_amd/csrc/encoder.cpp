@@ -114,9 +114,9 @@ std::vector<KeyCount> histogram(const std::vector<uint64_t> &keys, int threads) 
 
 // ------------------------------------------------------------ table fitting
 // Multiplicities maximising sum c_i log m_i subject to sum m_i <= K and
-// 1 <= m_i <= M: greedy increments by marginal gain (optimal for this
+// 1 <= m_i <= cap (cap <= M): greedy increments by marginal gain (optimal for this
 // separable concave objective).  Returns the coded bits sum c_i log2(K/m_i).
-double allocate(const std::vector<int64_t> &c, std::vector<int> &mult) {
+double allocate(const std::vector<int64_t> &c, std::vector<int> &mult, int cap) {
     const size_t q = c.size();
     mult.assign(q, 1);
     int left = kSlots - (int)q;
@@ -130,7 +130,7 @@ double allocate(const std::vector<int64_t> &c, std::vector<int> &mult) {
         int i = g.second;
         mult[i]++;
         --left;
-        if (mult[i] < kMaxBase)
+        if (mult[i] < cap)
             heap.push({(double)c[i] * log2((mult[i] + 1.0) / mult[i]), i});
     }
     double bits = 0;
@@ -151,7 +151,7 @@ struct Fit {
 // Choose which symbols get table slots and their multiplicities so that the
 // expected encoded size (coded bits + raw bits of escaped symbols) is
 // smallest over a search of the table size.
-Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta) {
+Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta, int cap) {
     std::vector<KeyCount> cand;
     int64_t forced_esc = 0;
     for (const auto &kc : hist) {
@@ -178,7 +178,7 @@ Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta)
         for (int i = 0; i < t; ++i) c[i] = cand[i].count;
         if (esc > 0) c.push_back(esc);
         std::vector<int> mult;
-        double bits = allocate(c, mult) + (double)esc * raw_bits;
+        double bits = allocate(c, mult, cap) + (double)esc * raw_bits;
         if (out) {
             out->keys.resize(t);
             out->counts.resize(t);
@@ -440,8 +440,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
             for (int64_t g = b; g < e; ++g) vkey[g] = v[g];
         }
     });
-    Fit dfit = fit_alphabet(histogram(dkey, threads), 32, true);
-    Fit vfit = fit_alphabet(histogram(vkey, threads), dtype == kF64 ? 64 : 32, false);
+    Fit dfit = fit_alphabet(histogram(dkey, threads), 32, true, (int)p.max_mult);
+    Fit vfit = fit_alphabet(histogram(vkey, threads), dtype == kF64 ? 64 : 32, false, (int)p.max_mult);
     SlotMap dsm, vsm;
     build_table(dfit, p.seed, c.dtab, dsm);
     build_table(vfit, p.seed ^ 0xd1b54a32d192ed03ull, c.vtab, vsm);
@@ -864,19 +864,32 @@ void nnz_layout_meta(const Container &c, std::vector<int32_t> &lane_row,
     }
 }
 
-void gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values) {
+bool gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values) {
     entry.assign(kSlots, 0);
     const size_t vb = c.value_bytes();
     values.assign(kSlots * vb, 0);
+    bool direct = true;
+    for (int i = 0; i < kSlots; ++i) {
+        if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))
+            direct = false;
+    }
+    // base - 1 (general) or the base itself (direct); unused slots: base 1
+    auto meta = [&](uint32_t base, uint32_t digit) -> uint64_t {
+        return (direct ? base : base - 1) | (digit << 8);
+    };
     for (int i = 0; i < kSlots; ++i) {
         uint64_t e = 0;
+        e |= meta(1, 0) << 32;
+        e |= meta(1, 0) << 48;
         if (c.dtab.flags[i] & 1) {
+            e &= ~(0xffffull << 32);
             e |= (c.dtab.flags[i] & 2) ? (1ull << 31) : (c.dtab.sym[i] & (kDeltaLimit - 1));
-            e |= (uint64_t)((c.dtab.base[i] - 1) | (c.dtab.digit[i] << 8)) << 32;
+            e |= meta(c.dtab.base[i], c.dtab.digit[i]) << 32;
         }
         if (c.vtab.flags[i] & 1) {
+            e &= ~(0xffffull << 48);
             if (c.vtab.flags[i] & 2) e |= 1ull << 30;
-            e |= (uint64_t)((c.vtab.base[i] - 1) | (c.vtab.digit[i] << 8)) << 48;
+            e |= meta(c.vtab.base[i], c.vtab.digit[i]) << 48;
             if (!(c.vtab.flags[i] & 2)) {
                 if (vb == 8) memcpy(&values[8 * i], &c.vtab.sym[i], 8);
                 else { uint32_t x = (uint32_t)c.vtab.sym[i]; memcpy(&values[4 * i], &x, 4); }
@@ -884,6 +897,7 @@ void gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uin
         }
         entry[i] = e;
     }
+    return direct;
 }
 
 }  // namespace dtans

@@ -476,7 +476,8 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
 
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
 // nonzeros of this thread's lane to a sink constructed here.
-template <int LAYOUT, typename VT, class Sink, class Src>
+// BD: "direct" tables (every base at most 255, stored as is; see dtans_core.hpp)
+template <int LAYOUT, typename VT, class Sink, class Src, bool BD>
 __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
                                              const VT *__restrict__ tval, int64_t slice,
                                              uint32_t lane, const typename Sink::Params &sp,
@@ -527,12 +528,19 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         // that do not load read a neighbouring word of the stream.
         if (j + 1 < Smax) {
             uint32_t D, Rm1, x1, x2;
-            group4((uint32_t)(e[0] >> 32) & 0xffffu, (uint32_t)(e[1] >> 48),
-                   (uint32_t)(e[2] >> 32) & 0xffffu, (uint32_t)(e[3] >> 48), D, Rm1);
-            const bool ext1 = append_and_check(d, r, D, Rm1, x1);
-            group4((uint32_t)(e[4] >> 32) & 0xffffu, (uint32_t)(e[5] >> 48),
-                   (uint32_t)(e[6] >> 32) & 0xffffu, (uint32_t)(e[7] >> 48), D, Rm1);
-            const bool ext2 = append_and_check(d, r, D, Rm1, x2);
+            auto group = [&](int q, uint32_t &x) {
+                const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
+                const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
+                if constexpr (BD) {
+                    group4_direct(m0, m1, m2, m3, D, Rm1);
+                    return append_direct(d, r, D, Rm1, x);
+                } else {
+                    group4(m0, m1, m2, m3, D, Rm1);
+                    return append_and_check(d, r, D, Rm1, x);
+                }
+            };
+            const bool ext1 = group(0, x1);
+            const bool ext2 = group(4, x2);
             // masks combined on the scalar unit: a ballot of a plain compare
             // is the compare's own lane mask
             const uint64_t m3 = ballot(more);
@@ -640,14 +648,14 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
 }
 
 // one encoded wave read straight from device memory
-template <int LAYOUT, typename VT, class Sink>
+template <int LAYOUT, typename VT, class Sink, bool BD>
 __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint64_t *tab,
                                                     const VT *tval, int64_t slice, uint32_t lane,
                                                     const typename Sink::Params &sp) {
     GlobalWords src{(const char *)(a.words + a.woff[slice])};
     Cursor<VT> cur{0, 0, 0, a.escd + a.doff[slice], (const VT *)a.escv + a.voff[slice]};
     const LaneGeo geo = lane_geo<LAYOUT>(a, slice, lane, lane_first_row<LAYOUT>(a, slice, lane));
-    decode_slice<LAYOUT, VT, Sink>(a, tab, tval, slice, lane, sp, src, cur, geo);
+    decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, tab, tval, slice, lane, sp, src, cur, geo);
 }
 
 template <typename VT>
@@ -662,7 +670,7 @@ __device__ __forceinline__ void stage_tables(const DevMat &a, uint64_t *s_tab, V
 
 // MINW: waves per SIMD the register allocation must allow (8 lets two
 // 16-wave workgroups share a CU, which is what the LDS tables permit)
-template <int LAYOUT, typename VT, class Sink, int MINW>
+template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
 __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
@@ -684,7 +692,7 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const int64_t stride = xcd_blocks * wpb;
     const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     for (int64_t s = s0; s < s_end; s += stride)
-        decode_slice_global<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp);
+        decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
 }
 
 // Same work as decode_kernel, with every wavefront owning one contiguous run
@@ -692,7 +700,7 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
 // them through an LDS ring (RingWords).  The XCD shares are those of
 // decode_kernel; inside a share the runs are consecutive, which keeps the
 // rows an XCD works on within a window of its share.
-template <int LAYOUT, typename VT, class Sink, int MINW>
+template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
 __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
@@ -725,7 +733,8 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
         const int32_t fr2 = s + 2 < sb ? lane_first_row<LAYOUT>(a, s + 2, lane) : 0;
         LaneGeo next{0, 0, 0, 0, 0, 0};
         if (s + 1 < sb) next = lane_geo<LAYOUT>(a, s + 1, lane, fr1);
-        decode_slice<LAYOUT, VT, Sink>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        decode_slice<LAYOUT, VT, Sink, RingWords<kRingWords>, BD>(a, s_tab, s_val, s, lane, sp, src, cur,
+                                                                 geo);
         geo = next;
         fr1 = fr2;
     }
@@ -834,8 +843,12 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         sp.alpha = alpha;
         sp.beta = beta;
         for (int w = wib; w < task.num_waves; w += wpb)
-            decode_slice_global<1, VT, SpmmSink<VT, 1, true>>(a, s_tab, s_val, task.first_wave + w,
-                                                              lane, sp);
+            if (a.base_direct)
+                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, true>(a, s_tab, s_val,
+                                                                        task.first_wave + w, lane, sp);
+            else
+                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, false>(a, s_tab, s_val,
+                                                                         task.first_wave + w, lane, sp);
     }
 }
 
@@ -1021,6 +1034,12 @@ hipError_t for_kc(int k, int kcmax, F f) {
     return hipSuccess;
 }
 
+// the kernel instance for the matrix's table format
+template <typename K>
+K pick_bd(const DevMat &a, K direct, K general) {
+    return a.base_direct ? direct : general;
+}
+
 template <typename VT>
 hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, int64_t ldy,
                      double alpha, double beta, double *partial, Launch L, hipStream_t st) {
@@ -1046,11 +1065,13 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         sp.alpha = alpha;
         sp.beta = beta;
         if (a.layout == 1)
-            hipLaunchKernelGGL((decode_kernel<1, VT, SinkT, SinkT::kOcc>), dim3(L.grid), block, 0,
-                               st, a, sp);
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, SinkT, SinkT::kOcc, true>,
+                                       decode_kernel<1, VT, SinkT, SinkT::kOcc, false>),
+                               dim3(L.grid), block, 0, st, a, sp);
         else
-            hipLaunchKernelGGL((decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc)>), dim3(L.grid),
-                               block, 0, st, a, sp);
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), true>,
+                                       decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), false>),
+                               dim3(L.grid), block, 0, st, a, sp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (a.layout == 2 && a.nsplit > 0) {
@@ -1096,8 +1117,11 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
             };
             typedef SpmmSink<VT, 1, true, double, 1> RowSink;
             typedef SpmmSink<VT, 1, true, double, 2> NnzSink;
-            if (a.layout == 1) return ring(TypeBox<RowSink>(), ring_kernel<1, VT, RowSink, 4>);
-            return ring(TypeBox<NnzSink>(), ring_kernel<2, VT, NnzSink, 4>);
+            if (a.layout == 1)
+                return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, true>,
+                                                        ring_kernel<1, VT, RowSink, 4, false>));
+            return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, true>,
+                                                    ring_kernel<2, VT, NnzSink, 4, false>));
         }
         return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
     }
@@ -1136,10 +1160,14 @@ hipError_t spmm_t_impl(const DevMat &a, int k, const VT *dY, int64_t lddy, VT *d
         sp.alpha = alpha;
         const dim3 block(64 * L.waves_per_wg);
         if (a.layout == 1)
-            hipLaunchKernelGGL((decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc>), dim3(L.grid), block, 0,
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, true>,
+                                       decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, false>),
+                               dim3(L.grid), block, 0,
                                st, a, sp);
         else
-            hipLaunchKernelGGL((decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc)>), dim3(L.grid), block, 0,
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), true>,
+                                       decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), false>),
+                               dim3(L.grid), block, 0,
                                st, a, sp);
         return hipGetLastError();
     });
@@ -1153,9 +1181,13 @@ hipError_t decode_impl(const DevMat &a, int32_t *col, void *vals, Launch L, hipS
     sp.vals = (typename Bits<VT>::T *)vals;
     const dim3 block(64 * L.waves_per_wg);
     if (a.layout == 1)
-        hipLaunchKernelGGL((decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc>), dim3(L.grid), block, 0, st, a, sp);
+        hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, true>,
+                                   decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, false>),
+                           dim3(L.grid), block, 0, st, a, sp);
     else
-        hipLaunchKernelGGL((decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc)>), dim3(L.grid), block, 0, st, a, sp);
+        hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), true>,
+                                   decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), false>),
+                           dim3(L.grid), block, 0, st, a, sp);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ struct DevMat {
     const int32_t *split_row, *split_first, *split_last;  // layout NNZ
     int64_t m, n, nnz, num_lanes, num_waves, nsplit;
     int32_t lane_nnz, layout;  // layout: 1 row per lane, 2 nonzeros per lane
+    int32_t base_direct;       // 1: table metadata holds bases, not bases - 1
 };
 
 struct Launch {

@@ -141,6 +141,33 @@ def test_spmv_stream_stages_agree(case, layout, T, dtype):
     check_spmv(ys[1].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, dtype)
 
 
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layout,T", [("row", 0), ("nnz", 32)])
+def test_table_formats_agree(case, layout, T):
+    """Tables capped at 255 slots per symbol (bases used as stored) and at the
+    paper's 256 (bases stored minus one) decode to the same CSR and give the
+    same products bit for bit, through SpMV, SpMM, the transpose and decode."""
+    torch = need_gpu()
+    name, rp, ci, v, n = CASES[case]
+    m = len(rp) - 1
+    x = torch.from_numpy(workloads.vector(n, 7)).cuda()
+    X = torch.from_numpy(workloads.vector(n, 9, k=3)).cuda()
+    dY = torch.from_numpy(workloads.vector(m, 10, k=2)).cuda()
+    out = []
+    for cap in (0, 256):
+        progress("table format %s %s T=%d cap=%d" % (name, layout, T, cap))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T, max_mult=cap)
+        if cap == 0:
+            assert A.info()["direct_table"] == 1
+        r2, c2, v2 = A.decode_csr()
+        assert np.array_equal(c2.cpu().numpy(), ci)
+        assert np.array_equal(v2.cpu().numpy(), v)
+        out.append((A.spmv(x), A.spmm(X), A.spmm_t(dY)))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    check_spmv(out[0][0].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, np.float64)
+
+
 @pytest.mark.parametrize("layout,T", LAYOUTS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("k", [1, 3, 8, 32, 37])

@@ -186,8 +186,36 @@ def test_all_bases_256_word_count():
     rows = [list(range(1, 4 * S + 1))] * m
     rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
     ci = np.array([c for r in rows for c in r], np.int32)
-    A = P.Matrix.from_csr(rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row")
+    A = P.Matrix.from_csr(rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row", max_mult=256)
     assert A.info()["words"] == m * (S + 2)
+    assert A.info()["direct_table"] == 0
+
+
+def test_multiplicity_cap():
+    """max_mult caps every symbol's slot count: with the default cap of 255 the
+    device table holds the bases directly; a single dominant symbol gets 255
+    slots (not 256), which costs a little more than the 4-bit floor; the
+    encoding still round-trips through the oracle's decoder."""
+    S, m = 9, 64
+    rows = [list(range(1, 4 * S + 1))] * m
+    rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
+    ci = np.array([c for r in rows for c in r], np.int32)
+    v = np.ones(len(ci))
+    A = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row")
+    B = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row", max_mult=256)
+    assert A.info()["direct_table"] == 1 and B.info()["direct_table"] == 0
+    assert B.info()["words"] <= A.info()["words"] <= m * (S + 3)
+    C = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row", max_mult=16)
+    assert C.info()["words"] > A.info()["words"]
+    for M in (A, B, C):
+        import tempfile, os
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "m.dtans")
+            M.save(path)
+            r2, c2, v2 = oracle.decode(path)
+            assert np.array_equal(c2, ci) and np.array_equal(v2, v)
+    with pytest.raises(P.DtansError):
+        P.Matrix.from_csr(rp, ci, v, 4 * S + 1, max_mult=257)
 
 
 def test_compression_closed_form_bound():
