@@ -83,6 +83,7 @@ struct dtans_matrix {
     std::vector<uint64_t> gtab;
     std::vector<uint8_t> gval;
     std::vector<int32_t> lane_row, split_row, split_first, split_last;
+    std::vector<int32_t> nzr, empty_rows;  // layout NNZ: {row, end} pairs; rows without nonzeros
     DevBufs bufs;
     bool uploaded = false;
     int device = -1, num_cus = 256;
@@ -114,6 +115,35 @@ struct dtans_csr {
 };
 
 namespace {
+
+// Layout NNZ: the list of nonempty rows as {row, end} pairs with a {m, nnz}
+// sentinel, the rows without nonzeros, and lane_row rewritten from a row to
+// its index in the list (a lane's first nonzero always lies in a nonempty row).
+void nonempty_rows(const Container &c, std::vector<int32_t> &lane_row, std::vector<int32_t> &nzr,
+                   std::vector<int32_t> &empty) {
+    nzr.clear();
+    empty.clear();
+    if (c.layout != kLayoutNnz) return;
+    std::vector<int32_t> index(c.m, -1);
+    for (int64_t i = 0; i < c.m; ++i) {
+        if (c.row_ptr[i] < c.row_ptr[i + 1]) {
+            index[i] = (int32_t)(nzr.size() / 2);
+            nzr.push_back((int32_t)i);
+            nzr.push_back(c.row_ptr[i + 1]);
+        } else {
+            empty.push_back((int32_t)i);
+        }
+    }
+    nzr.push_back((int32_t)c.m);
+    nzr.push_back((int32_t)c.nnz);
+    for (auto &r : lane_row) {
+        // lane 0 is listed at row 0, which may be empty: its first nonzero
+        // lies in the first nonempty row
+        int64_t i = r;
+        while (i < c.m && index[i] < 0) ++i;
+        r = i < c.m ? index[i] : (int32_t)(nzr.size() / 2 - 1);
+    }
+}
 
 // SpMV stages its streams through an LDS ring only when asked to (measured:
 // the direct-read kernels, at twice the waves per SIMD, are faster on the
@@ -160,6 +190,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     const Container &c = h->c;
     const bool direct = gpu_table(c, h->gtab, h->gval);
     nnz_layout_meta(c, h->lane_row, h->split_row, h->split_first, h->split_last);
+    nonempty_rows(c, h->lane_row, h->nzr, h->empty_rows);
     const bool f64 = c.dtype == kF64;
     const void *escv_src = c.escv.data();
     size_t escv_bytes = c.escv.size() * 8;
@@ -170,7 +201,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
         escv_src = escv32.data();
         escv_bytes = escv32.size() * 4;
     }
-    void *p[13];
+    void *p[15];
     HIP_TRY(h->bufs.upload(&p[0], h->gtab.data(), 8 * h->gtab.size(), st));
     HIP_TRY(h->bufs.upload(&p[1], h->gval.data(), h->gval.size(), st));
     HIP_TRY(h->bufs.upload(&p[2], c.row_ptr.data(), 4 * c.row_ptr.size(), st));
@@ -184,6 +215,8 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     HIP_TRY(h->bufs.upload(&p[10], h->split_row.data(), 4 * h->split_row.size(), st));
     HIP_TRY(h->bufs.upload(&p[11], h->split_first.data(), 4 * h->split_first.size(), st));
     HIP_TRY(h->bufs.upload(&p[12], h->split_last.data(), 4 * h->split_last.size(), st));
+    HIP_TRY(h->bufs.upload(&p[13], h->nzr.data(), 4 * h->nzr.size(), st));
+    HIP_TRY(h->bufs.upload(&p[14], h->empty_rows.data(), 4 * h->empty_rows.size(), st));
     // the host staging vectors above must outlive the copies
     HIP_TRY(hipStreamSynchronize(st));
     DevMat &v = h->view;
@@ -197,6 +230,10 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.escd = (const uint32_t *)p[7];
     v.escv = p[8];
     v.lane_row = (const int32_t *)p[9];
+    v.nzr = (const int2 *)p[13];
+    v.empty_rows = (const int32_t *)p[14];
+    v.n_nzr = c.layout == kLayoutNnz ? (int64_t)h->nzr.size() / 2 - 1 : 0;
+    v.n_empty = (int64_t)h->empty_rows.size();
     v.split_row = (const int32_t *)p[10];
     v.split_first = (const int32_t *)p[11];
     v.split_last = (const int32_t *)p[12];
@@ -542,8 +579,15 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
         nnz_layout_meta(c, lr, sr, sf, sl);
         nsplit = (int64_t)sr.size();
     }
-    o->index_bytes = 4 * (c.m + 1) + 3 * 8 * (c.num_waves + 1) +
-                     (c.layout == kLayoutNnz ? 4 * c.num_lanes + 12 * nsplit : 0);
+    // what the kernels read besides tables and streams: row pointers (row
+    // layout) or the nonempty-row list and empty rows (nonzero layout), the
+    // per-wave offsets, and the lane and split-row lists
+    int64_t nonempty = 0;
+    for (int64_t i = 0; i < c.m; ++i) nonempty += c.row_ptr[i] < c.row_ptr[i + 1];
+    o->index_bytes = 3 * 8 * (c.num_waves + 1) +
+                     (c.layout == kLayoutNnz
+                          ? 8 * (nonempty + 1) + 4 * (c.m - nonempty) + 4 * c.num_lanes + 12 * nsplit
+                          : 4 * (c.m + 1));
     o->total_bytes = o->table_bytes + o->stream_bytes + o->index_bytes;
     o->csr_bytes = 4 * (c.m + 1) + c.nnz * (4 + vb);
     o->coo_bytes = c.nnz * (8 + vb);

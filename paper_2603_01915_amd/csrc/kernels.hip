@@ -58,8 +58,9 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
 //   finish_row(row, kind): the lane has seen its last nonzero of `row`; kind
 //     says whether the lane holds the whole row, its head (the row started in
 //     an earlier lane) or its tail (the row continues in later lanes).
-//   empty_row(row): a row without nonzeros that this lane owns.
-// Rows that end in the middle of a lane are finished inside segment().
+// Rows that end in the middle of a lane are finished inside segment().  Rows
+// without nonzeros are a lane of their own in the row layout (finish_row with
+// no segment) and never visited in the nonzero layout.
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
@@ -93,7 +94,7 @@ struct SpmmSink {
     int32_t prow[DEFER == 2 ? 4 : 1];             // its rows (DEFER 2)
     int pn;                                       // its nonzeros (0: none)
     // cur starts at -1: a row is finished only after the sink has seen one of
-    // its nonzeros (empty rows are written by the decoder via empty_row)
+    // its nonzeros
     __device__ SpmmSink(const Params &pp, int64_t l, int32_t first_row, bool first_is_head)
         : p(pp), lane(l), cur(-1), head_row(first_is_head ? first_row : -1), pn(0) {
 #pragma unroll
@@ -249,11 +250,6 @@ struct SpmmSink {
         consume();
         store(row, kind);
     }
-    __device__ __forceinline__ void empty_row(int32_t row) {
-        VT *y = UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy;
-#pragma unroll
-        for (int c = 0; c < KC; ++c) y[c] = p.beta == 0.0 ? (VT)0 : (VT)(p.beta * (double)y[c]);
-    }
 };
 
 // dX (k columns) += alpha * A^T dY, scattered with atomic adds.
@@ -293,7 +289,6 @@ struct TransSink {
     }
     __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
-    __device__ __forceinline__ void empty_row(int32_t) {}
 };
 
 // decode to CSR: column and value bits of every nonzero
@@ -318,7 +313,6 @@ struct DecodeSink {
     }
     __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
-    __device__ __forceinline__ void empty_row(int32_t) {}
 };
 
 // --------------------------------------------------------- wave decoding
@@ -436,13 +430,19 @@ struct Cursor {
 };
 
 // Where a lane's stream sits in the matrix: its first nonzero g0 and count;
-// its first row with that row's [beg, end) and the end of the row after it
-// (layout NNZ).  The nonzero layout needs two dependent loads (lane_row, then
-// row_ptr), so callers may issue the first a wave ahead (lane_first_row).
+// the row of that nonzero with the row's [beg, end).  The nonzero layout
+// walks the list of nonempty rows ({row, end} pairs, a sentinel {m, nnz} at
+// the end), so a lane never visits empty rows (their y is written by
+// empty_rows_kernel) and crosses exactly one row per nonzero that starts one;
+// it keeps the next two list entries loaded ahead (n1, n2).  Finding the
+// first entry takes two dependent loads (lane_row, then the list), so
+// callers may issue the first a wave ahead (lane_first_row).
 struct LaneGeo {
     int64_t g0;
     int cnt;
-    int32_t row, row_beg, row_end, next_end;
+    int32_t krow;  // layout NNZ: index of `row` in the nonempty-row list
+    int32_t row, row_beg, row_end;
+    int2 n1, n2;
 };
 
 template <int LAYOUT>
@@ -454,21 +454,25 @@ __device__ __forceinline__ int32_t lane_first_row(const DevMat &a, int64_t slice
 
 template <int LAYOUT>
 __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint32_t lane,
-                                            int32_t first_row) {
-    LaneGeo q{0, 0, 0, 0, 0, 0};
+                                            int32_t first) {
+    LaneGeo q{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0)};
     const int64_t l = slice * kWave + lane;
     if (l < a.num_lanes) {
-        q.row = first_row;
         if (LAYOUT == 1) {
+            q.row = first;
             q.row_beg = a.row_ptr[l];
             q.cnt = a.row_ptr[l + 1] - q.row_beg;
             q.g0 = q.row_beg;
         } else {
             q.g0 = l * (int64_t)a.lane_nnz;
             q.cnt = (int)min((int64_t)a.lane_nnz, a.nnz - q.g0);
-            q.row_beg = a.row_ptr[first_row];
-            q.row_end = a.row_ptr[first_row + 1];
-            q.next_end = first_row + 2 <= a.m ? a.row_ptr[first_row + 2] : (int32_t)a.nnz;
+            q.krow = first;
+            const int2 c = a.nzr[first];
+            q.row = c.x;
+            q.row_end = c.y;
+            q.row_beg = first > 0 ? a.nzr[first - 1].y : 0;
+            q.n1 = a.nzr[min((int64_t)first + 1, a.n_nzr)];
+            q.n2 = a.nzr[min((int64_t)first + 2, a.n_nzr)];
         }
     }
     return q;
@@ -486,7 +490,8 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     const bool live = l < a.num_lanes;
     const int64_t g0 = geo.g0;
     const int cnt = geo.cnt;
-    int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, next_end = geo.next_end;
+    int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, krow = geo.krow;
+    int2 n1 = geo.n1, n2 = geo.n2;
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
     const int S = (cnt + 3) >> 2;
     const int Smax = __builtin_amdgcn_readfirstlane(wave_max(S));  // uniform: scalar loop
@@ -604,19 +609,18 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             sink.template segment<false>(cols, v, nreal, g, rowk);
         } else {
             // resolve row boundaries first: a column delta restarts at every
-            // row; empty rows passed over are written here, rows with
-            // nonzeros are finished by the sink when their successor starts
+            // row; a nonzero at the end of the current row starts the next
+            // nonempty one, whose predecessor the sink finishes
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (k < nreal) {
-                    while (g + k >= row_end) {
-                        if (row_beg == row_end) sink.empty_row(row);
-                        ++row;
-                        row_beg = row_end;
-                        row_end = next_end;
-                        next_end = row + 2 <= a.m ? a.row_ptr[row + 2] : (int32_t)a.nnz;
-                        col = 0;
-                    }
+                if (k < nreal && g + k >= row_end) {
+                    ++krow;
+                    row_beg = row_end;
+                    row = n1.x;
+                    row_end = n1.y;
+                    n1 = n2;
+                    n2 = a.nzr[min((int64_t)krow + 2, a.n_nzr)];
+                    col = 0;
                 }
                 col += dl[k];
                 cols[k] = col;
@@ -633,17 +637,10 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     if (LAYOUT == 1) {
         if (l < a.m) sink.finish_row(row, kComplete);
     } else {
+        // `row` holds this lane's last nonzeros: complete when it ends here,
+        // else a tail (or, started in an earlier lane, a head) to be summed
         const int64_t gend = g0 + cnt;
-        bool first = true;  // `row` holds this lane's last nonzeros
-        while (row < a.m && row_end <= gend) {  // rows finished here, incl. empty ones
-            if (first) sink.finish_row(row, row_beg < g0 ? kHead : kComplete);
-            else sink.empty_row(row);
-            first = false;
-            ++row;
-            row_beg = row_end;
-            if (row < a.m) row_end = a.row_ptr[row + 1];
-        }
-        if (first && row < a.m) sink.finish_row(row, row_beg < g0 ? kHead : kTail);
+        sink.finish_row(row, row_beg < g0 ? kHead : (row_end <= gend ? kComplete : kTail));
     }
 }
 
@@ -810,6 +807,16 @@ __global__ __launch_bounds__(256) void flush_kernel(const uint4 *p, int64_t n, u
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     if (acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads; the buffer is zero
+}
+
+// layout NNZ: y = beta * y on the rows without nonzeros (never decoded)
+template <typename VT>
+__global__ void empty_rows_kernel(const int32_t *rows, int64_t count, VT *Y, int KC, int64_t ldy,
+                                  double beta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count * KC) return;
+    VT *y = Y + (int64_t)rows[i / KC] * ldy + i % KC;
+    *y = beta == 0.0 ? (VT)0 : (VT)(beta * (double)*y);
 }
 
 // ------------------------------------------------- multi-matrix launch
@@ -1034,6 +1041,27 @@ hipError_t for_kc(int k, int kcmax, F f) {
     return hipSuccess;
 }
 
+// layout NNZ after the decode: rows split over lanes, then rows without
+// nonzeros (both only write y)
+template <typename VT>
+hipError_t nnz_epilogue(const DevMat &a, const double *partial, int KC, VT *Y, int64_t ldy,
+                        double alpha, double beta, hipStream_t st) {
+    if (a.nsplit > 0) {
+        hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256), 0, st,
+                           a.split_row, a.split_first, a.split_last, a.nsplit, partial, KC, Y, ldy,
+                           alpha, beta);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.n_empty > 0) {
+        const int64_t tot = a.n_empty * KC;
+        hipLaunchKernelGGL(empty_rows_kernel<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                           a.empty_rows, a.n_empty, Y, KC, ldy, beta);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
 // the kernel instance for the matrix's table format
 template <typename K>
 K pick_bd(const DevMat &a, K direct, K general) {
@@ -1073,14 +1101,8 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
                                        decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), false>),
                                dim3(L.grid), block, 0, st, a, sp);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (a.layout == 2 && a.nsplit > 0) {
-            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256), 0,
-                               st, a.split_row, a.split_first, a.split_last, a.nsplit, partial, KC,
-                               Y + c0, ldy, alpha, beta);
-            e = hipGetLastError();
-        }
-        return e;
+        if (e != hipSuccess || a.layout != 2) return e;
+        return nnz_epilogue(a, partial, KC, Y + c0, ldy, alpha, beta, st);
     };
     if (k == 1 && ldx == 1 && ldy == 1 && a.n * (int64_t)sizeof(VT) <= (1ll << 32)) {
         if (L.ring) {
@@ -1109,11 +1131,8 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
                     (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
                 hipLaunchKernelGGL(kern, dim3(grid), block, lds, st, a, sp);
                 hipError_t e = hipGetLastError();
-                if (e != hipSuccess || a.layout != 2 || a.nsplit == 0) return e;
-                hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256),
-                                   0, st, a.split_row, a.split_first, a.split_last, a.nsplit, partial,
-                                   1, Y, ldy, alpha, beta);
-                return hipGetLastError();
+                if (e != hipSuccess || a.layout != 2) return e;
+                return nnz_epilogue(a, partial, 1, Y, ldy, alpha, beta, st);
             };
             typedef SpmmSink<VT, 1, true, double, 1> RowSink;
             typedef SpmmSink<VT, 1, true, double, 2> NnzSink;

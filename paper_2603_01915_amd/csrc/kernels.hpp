@@ -15,9 +15,12 @@ struct DevMat {
     const uint32_t *words;
     const uint32_t *escd;
     const void *escv;        // raw escaped values (float or double)
-    const int32_t *lane_row; // layout NNZ: row holding each lane's first nonzero
+    const int32_t *lane_row; // layout NNZ: index in nzr of the row of each lane's first nonzero
     const int32_t *split_row, *split_first, *split_last;  // layout NNZ
+    const int2 *nzr;         // layout NNZ: {row, end} of every nonempty row, then {m, nnz}
+    const int32_t *empty_rows;  // layout NNZ: the rows without nonzeros
     int64_t m, n, nnz, num_lanes, num_waves, nsplit;
+    int64_t n_nzr, n_empty;    // layout NNZ: nonempty rows (nzr has n_nzr + 1 entries), empty rows
     int32_t lane_nnz, layout;  // layout: 1 row per lane, 2 nonzeros per lane
     int32_t base_direct;       // 1: table metadata holds bases, not bases - 1
 };
