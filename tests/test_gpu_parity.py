@@ -146,7 +146,8 @@ def test_spmv_stream_stages_agree(case, layout, T, dtype):
 def test_table_formats_agree(case, layout, T):
     """Tables capped at 255 slots per symbol (bases used as stored) and at the
     paper's 256 (bases stored minus one) decode to the same CSR and give the
-    same products bit for bit, through SpMV, SpMM, the transpose and decode."""
+    same products bit for bit through SpMV and SpMM; the transpose (atomic
+    adds, order not fixed) agrees within the tolerance."""
     torch = need_gpu()
     name, rp, ci, v, n = CASES[case]
     m = len(rp) - 1
@@ -163,9 +164,17 @@ def test_table_formats_agree(case, layout, T):
         assert np.array_equal(c2.cpu().numpy(), ci)
         assert np.array_equal(v2.cpu().numpy(), v)
         out.append((A.spmv(x), A.spmm(X), A.spmm_t(dY)))
-    for a, b in zip(out[0], out[1]):
+    for a, b in zip(out[0][:2], out[1][:2]):
         assert torch.equal(a, b)
     check_spmv(out[0][0].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, np.float64)
+    At = sp.csr_matrix((v, ci, rp), shape=(m, n)).T.tocsr()
+    At.sort_indices()
+    dYh = dY.cpu().numpy()
+    for c in range(2):
+        ref = oracle.spmtv(rp, ci, v, n, dYh[:, c])
+        scale = oracle.absmv(At.indptr, At.indices, At.data, dYh[:, c])
+        for o in out:
+            assert rel_error(o[2].cpu().numpy()[:, c], ref, scale) <= TOL[np.float64]
 
 
 @pytest.mark.parametrize("layout,T", LAYOUTS)
