@@ -151,9 +151,10 @@ def test_table_formats_agree(case, layout, T):
     torch = need_gpu()
     name, rp, ci, v, n = CASES[case]
     m = len(rp) - 1
-    x = torch.from_numpy(workloads.vector(n, 7)).cuda()
-    X = torch.from_numpy(workloads.vector(n, 9, k=3)).cuda()
-    dY = torch.from_numpy(workloads.vector(m, 10, k=2)).cuda()
+    dt = v.dtype
+    x = torch.from_numpy(workloads.vector(n, 7, dt)).cuda()
+    X = torch.from_numpy(workloads.vector(n, 9, dt, k=3)).cuda()
+    dY = torch.from_numpy(workloads.vector(m, 10, dt, k=2)).cuda()
     out = []
     for cap in (0, 256):
         progress("table format %s %s T=%d cap=%d" % (name, layout, T, cap))
@@ -166,15 +167,15 @@ def test_table_formats_agree(case, layout, T):
         out.append((A.spmv(x), A.spmm(X), A.spmm_t(dY)))
     for a, b in zip(out[0][:2], out[1][:2]):
         assert torch.equal(a, b)
-    check_spmv(out[0][0].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, np.float64)
-    At = sp.csr_matrix((v, ci, rp), shape=(m, n)).T.tocsr()
+    check_spmv(out[0][0].cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, dt.type)
+    At = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
     At.sort_indices()
     dYh = dY.cpu().numpy()
     for c in range(2):
         ref = oracle.spmtv(rp, ci, v, n, dYh[:, c])
         scale = oracle.absmv(At.indptr, At.indices, At.data, dYh[:, c])
         for o in out:
-            assert rel_error(o[2].cpu().numpy()[:, c], ref, scale) <= TOL[np.float64]
+            assert rel_error(o[2].cpu().numpy()[:, c], ref, scale) <= TOL[dt.type]
 
 
 @pytest.mark.parametrize("layout,T", LAYOUTS)
