@@ -75,7 +75,9 @@ typedef struct {
     int32_t max_mult;      /* largest number of slots per symbol, 1..256 (Sec. IV-C's
                               cap M = 256); 0 = 255, which keeps every base within a
                               byte so that the kernels use it without a correction */
-    int32_t reserved;
+    int32_t first_delta_column; /* 1: the first delta of a row is its column (Sec. IV-A);
+                              0: column - row + 2^29 (mod 2^32), which banded and
+                              stencil matrices keep within the table */
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -96,6 +98,8 @@ typedef struct {
     double bits_per_nnz;                   /* 8 * stream_bytes / nnz */
     int32_t stream_stage;                  /* SpMV word reads: 1 direct, 2 LDS ring */
     int32_t direct_table;                  /* 1: every base <= 255, used without correction */
+    int32_t first_delta_column;            /* 1: first deltas are columns (the paper's form) */
+    int32_t reserved;
 } dtans_info;
 
 typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */

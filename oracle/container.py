@@ -35,6 +35,7 @@ K = 4096
 M = 256
 WAVE = 64
 DELTA_LIMIT = 1 << 30
+FIRST_BIAS = 1 << 29  # first-delta mode 1 (an extension of the paper's format)
 HEADER = 256
 ESC = "ESC"
 
@@ -68,6 +69,7 @@ class Container:
     words: np.ndarray
     escd: np.ndarray
     escv: np.ndarray
+    first_mode: int = 0  # first delta of a row: 0 its column, 1 column - row + 2^29
 
 
 def _al8(x: int) -> int:
@@ -129,8 +131,11 @@ def read(path: str, verify: bool = True) -> Container:
     escv = take("<u8" if dtype == 2 else "<u4", nv)
     if o != len(data):
         raise ValueError("size mismatch")
+    (first_mode,) = struct.unpack_from("<I", data, 104)
+    if first_mode > 1:
+        raise ValueError("bad first-delta mode")
     return Container(dtype, layout, T, m, n, nnz, lanes, waves, seed, dtab, vtab,
-                     row_ptr, woff, doff, voff, words, escd, escv)
+                     row_ptr, woff, doff, voff, words, escd, escv, first_mode)
 
 
 def write(path: str, c: Container) -> None:
@@ -156,6 +161,7 @@ def write(path: str, c: Container) -> None:
     struct.pack_into("<qqqqqqqqQQ", hdr, 24, c.m, c.n, c.nnz, c.num_lanes, c.num_waves,
                      len(c.words), len(c.escd), len(c.escv), c.seed,
                      _fnv1a64_np(np.frombuffer(bytes(body), np.uint8)))
+    struct.pack_into("<I", hdr, 104, c.first_mode)
     with open(path, "wb") as f:
         f.write(bytes(hdr) + bytes(body))
 
@@ -170,16 +176,31 @@ def lane_ranges(layout: int, lane_nnz: int, m: int, nnz: int, row_ptr) -> List[t
     return [(l * lane_nnz, min(lane_nnz, nnz - l * lane_nnz)) for l in range(lanes)]
 
 
-def delta_keys(row_ptr, col, ranges) -> List[int]:
-    """Column delta per nonzero: the column itself for the first nonzero of a
-    row or of a lane stream, else the difference to the previous column
-    (Sec. IV-A: rows are delta-encoded separately)."""
+def row_of(row_ptr, g: int) -> int:
+    """The row holding nonzero g (the last i with row_ptr[i] <= g)."""
+    return int(np.searchsorted(np.asarray(row_ptr), g, side="right")) - 1
+
+
+def first_base(first_mode: int, row: int) -> int:
+    """Start value of a row's column accumulation: 0 (mode 0, the paper's form)
+    or row - 2^29 modulo 2^32 (mode 1)."""
+    return (row - FIRST_BIAS) % (1 << 32) if first_mode else 0
+
+
+def delta_keys(row_ptr, col, ranges, first_mode: int = 0) -> List[int]:
+    """Column delta per nonzero: for the first nonzero of a row or of a lane
+    stream the column itself (mode 0, Sec. IV-A) or column - row + 2^29 modulo
+    2^32 (mode 1), else the difference to the previous column (rows are
+    delta-encoded separately)."""
     first = set(int(row_ptr[i]) for i in range(len(row_ptr) - 1) if row_ptr[i] < row_ptr[i + 1])
     d = [0] * len(col)
     for g0, c in ranges:
         for t in range(c):
             g = g0 + t
-            d[g] = int(col[g]) if (t == 0 or g in first) else int(col[g]) - int(col[g - 1])
+            if t == 0 or g in first:
+                d[g] = (int(col[g]) - first_base(first_mode, row_of(row_ptr, g))) % (1 << 32)
+            else:
+                d[g] = int(col[g]) - int(col[g - 1])
     return d
 
 
@@ -233,7 +254,10 @@ def decode(c: Container):
                     if s == ESC:
                         s = int(c.escd[dp]); dp += 1
                     g = lanes[q][0] + t
-                    colv[q] = s if (t == 0 or g in first) else colv[q] + s
+                    if t == 0 or g in first:
+                        colv[q] = (first_base(c.first_mode, row_of(c.row_ptr, g)) + s) % (1 << 32)
+                    else:
+                        colv[q] = colv[q] + s
                     col[g] = colv[q]
             for pos in range(4):
                 for q in slots:
@@ -307,12 +331,12 @@ def simple_tables(dkeys, vkeys, seed: int):
 
 
 def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int = 0,
-           tables: Optional[tuple] = None, seed: int = 1) -> Container:
+           tables: Optional[tuple] = None, seed: int = 1, first_mode: int = 0) -> Container:
     p = toy.CSR_DTANS
     row_ptr = np.asarray(row_ptr, np.int64)
     nnz = int(row_ptr[-1])
     ranges = lane_ranges(layout, lane_nnz, m, nnz, row_ptr)
-    dk = delta_keys(row_ptr, col, ranges)
+    dk = delta_keys(row_ptr, col, ranges, first_mode)
     vk = value_keys(vals, dtype)
     dtab, vtab = tables if tables is not None else simple_tables(dk, vk, seed)
     tabs = (dtab, vtab)
@@ -380,4 +404,4 @@ def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int 
                      seed, dtab, vtab, row_ptr.astype(np.int32), np.array(woff, np.uint64),
                      np.array(doff, np.uint64), np.array(voff, np.uint64),
                      np.array(words, np.uint32), np.array(escd, np.uint32),
-                     np.array(escv, np.uint64 if dtype == 2 else np.uint32))
+                     np.array(escv, np.uint64 if dtype == 2 else np.uint32), first_mode)

@@ -291,7 +291,28 @@ typedef struct {
     uint32_t lane_nnz; /* T for layout 2 */
     int64_t m, n, nnz, num_lanes, num_waves, n_words, n_escd, n_escv;
     uint64_t seed;
+    uint32_t first_mode; /* first delta of a row: 0 its column, 1 column - row + 2^29 */
 } ohdr;
+
+/* First delta of a row (or of a lane starting inside a row), mode 1: the
+ * column minus the row plus 2^29, modulo 2^32 (an extension of the format:
+ * the paper's first delta is the column itself, Sec. IV-A). */
+#define ORC_FIRST_BIAS (1u << 29)
+static uint32_t first_base(uint32_t mode, int64_t row)
+{
+    return mode ? (uint32_t)row - ORC_FIRST_BIAS : 0u;
+}
+
+/* the row holding nonzero g: the last i with row_ptr[i] <= g */
+static int64_t row_of(const int32_t *row_ptr, int64_t m, int64_t g)
+{
+    int64_t lo = 0, hi = m; /* row_ptr[lo] <= g < row_ptr[hi] */
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (row_ptr[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
@@ -452,10 +473,10 @@ static void write_table(uint8_t *b, const otable *t)
  */
 int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
                   const int32_t *row_ptr, const int32_t *col, const void *vals,
-                  int dtype, int layout, int lane_nnz, uint64_t seed)
+                  int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode)
 {
     if (m < 0 || n < 0 || nnz < 0 || (dtype != 1 && dtype != 2) ||
-        (layout != 1 && layout != 2) ||
+        (layout != 1 && layout != 2) || (first_mode != 0 && first_mode != 1) ||
         (layout == 2 && (lane_nnz <= 0 || lane_nnz % 4 != 0)))
         return ORC_EINVAL;
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return ORC_EINVAL;
@@ -471,7 +492,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
     H.dtype = (uint32_t)dtype;
     H.layout = (uint32_t)layout;
     H.lane_nnz = layout == 2 ? (uint32_t)lane_nnz : 0;
-    H.m = m; H.n = n; H.nnz = nnz; H.seed = seed;
+    H.m = m; H.n = n; H.nnz = nnz; H.seed = seed; H.first_mode = (uint32_t)first_mode;
     H.num_lanes = layout == 1 ? m : (nnz + lane_nnz - 1) / lane_nnz;
     H.num_waves = (H.num_lanes + OK_WAVE - 1) / OK_WAVE;
 
@@ -484,8 +505,10 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         lane_range(&H, row_ptr, l, &g0, &c);
         for (int64_t t = 0; t < c; ++t) {
             int64_t g = g0 + t;
-            dkey[g] = (t == 0 || first[g]) ? (uint64_t)col[g]
-                                           : (uint64_t)(col[g] - col[g - 1]);
+            if (t == 0 || first[g])
+                dkey[g] = (uint32_t)col[g] - first_base(H.first_mode, row_of(row_ptr, m, g));
+            else
+                dkey[g] = (uint64_t)(col[g] - col[g - 1]);
         }
     }
     for (int64_t g = 0; g < nnz; ++g) {
@@ -631,6 +654,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         put_u64(buf + 72, (uint64_t)H.n_escd);
         put_u64(buf + 80, (uint64_t)H.n_escv);
         put_u64(buf + 88, H.seed);
+        put_u32(buf + 104, H.first_mode);
         put_u64(buf + 96, fnv1a64(buf + OK_HEADER, sz - OK_HEADER));
         FILE *fp = fopen(path, "wb");
         if (!fp || fwrite(buf, 1, sz, fp) != sz) rc = ORC_EIO;
@@ -687,6 +711,8 @@ static int read_file(const char *path, ofile *F)
     H->n_escd = (int64_t)get_u64(b + 72);
     H->n_escv = (int64_t)get_u64(b + 80);
     H->seed = get_u64(b + 88);
+    H->first_mode = get_u32(b + 104);
+    if (H->first_mode > 1) return ORC_ECORRUPT;
     if (fnv1a64(b + OK_HEADER, F->size - OK_HEADER) != get_u64(b + 96)) return ORC_ECORRUPT;
     if ((H->dtype != 1 && H->dtype != 2) || (H->layout != 1 && H->layout != 2)) return ORC_ECORRUPT;
     if (H->m < 0 || H->n < 0 || H->nnz < 0 || H->n_words < 0 || H->n_escd < 0 || H->n_escv < 0)
@@ -809,7 +835,10 @@ int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void
                         delta = td.sym[s];
                     }
                     int64_t g = g0[q] + t;
-                    uint64_t cc = (t == 0 || first[g]) ? delta : (uint64_t)colv[q] + delta;
+                    uint64_t cc = (t == 0 || first[g])
+                                      ? (uint32_t)(first_base(H->first_mode, row_of(F.row_ptr, H->m, g)) +
+                                                   (uint32_t)delta)
+                                      : (uint64_t)colv[q] + delta;
                     if (cc >= (uint64_t)H->n) { rc = ORC_ECORRUPT; goto wave_done; }
                     colv[q] = (uint32_t)cc;
                     col_out[g] = (int32_t)cc;
@@ -872,7 +901,7 @@ int oracle_read_header(const char *path, int64_t *out)
         out[3] = F.H.m; out[4] = F.H.n; out[5] = F.H.nnz;
         out[6] = F.H.num_lanes; out[7] = F.H.num_waves; out[8] = F.H.n_words;
         out[9] = F.H.n_escd; out[10] = F.H.n_escv; out[11] = (int64_t)F.H.seed;
-        out[12] = (int64_t)F.size;
+        out[12] = (int64_t)F.size; out[13] = F.H.first_mode;
     }
     free(F.buf);
     return rc;

@@ -98,7 +98,8 @@ class Matrix:
     @classmethod
     def from_csr(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
                  waves_per_wg: int = 0, wg_per_cu: int = 0, sort_rows: bool = False,
-                 seed: int = 1, stream_stage: int = 0, max_mult: int = 0) -> "Matrix":
+                 seed: int = 1, stream_stage: int = 0, max_mult: int = 0,
+                 first_delta_column: bool = False) -> "Matrix":
         L = _lib.load()
         rp = _np(row_ptr, np.int32)
         ci = _np(col, np.int32)
@@ -116,6 +117,7 @@ class Matrix:
         o.perm_seed = seed
         o.stream_stage = stream_stage
         o.max_mult = max_mult
+        o.first_delta_column = int(bool(first_delta_column))
         h = ctypes.c_void_p()
         _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
                                       ctypes.byref(o), ctypes.byref(h)))

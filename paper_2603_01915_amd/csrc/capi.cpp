@@ -246,6 +246,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.lane_nnz = (int32_t)c.lane_nnz;
     v.layout = (int32_t)c.layout;
     v.base_direct = direct ? 1 : 0;
+    v.first_mode = c.first_mode;
     h->device = dev;
     h->num_cus = device_cus(dev);
     h->uploaded = true;
@@ -501,6 +502,7 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     EncodeParams p;
     p.seed = o.perm_seed;
     p.max_mult = o.max_mult ? (uint32_t)o.max_mult : 255u;
+    p.first_mode = o.first_delta_column ? 0u : 1u;
     int layout = 0, T = 0;
     auto_encoding(m, nnz, row_ptr, o, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
@@ -600,6 +602,7 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->value_cross_entropy = c.vtab.cross_entropy;
     o->bits_per_nnz = c.nnz ? 8.0 * o->stream_bytes / c.nnz : 0.0;
     o->stream_stage = uses_ring(mat) ? DTANS_STAGE_RING : DTANS_STAGE_DIRECT;
+    o->first_delta_column = c.first_mode == 0;
     o->direct_table = 1;
     for (int i = 0; i < kSlots; ++i)
         if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))

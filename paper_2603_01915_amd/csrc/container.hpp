@@ -29,6 +29,7 @@ struct Table {
 
 struct Container {
     uint32_t dtype = kF64, layout = kLayoutRow, lane_nnz = 0;
+    uint32_t first_mode = 0;  // first delta of a row: 0 its column, 1 relative to the row
     int64_t m = 0, n = 0, nnz = 0, num_lanes = 0, num_waves = 0;
     uint64_t seed = 1;
     Table dtab, vtab;
@@ -52,10 +53,22 @@ struct Container {
     }
 };
 
+// the (nonempty) row holding nonzero g: the last i with row_ptr[i] <= g
+inline int64_t row_of(const std::vector<int32_t> &row_ptr, int64_t g) {
+    int64_t lo = 0, hi = (int64_t)row_ptr.size() - 1;  // row_ptr[lo] <= g < row_ptr[hi]
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (row_ptr[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 struct EncodeParams {
     uint32_t layout = kLayoutRow;
     uint32_t lane_nnz = 0;
     uint32_t max_mult = 255;  // multiplicity cap, at most M = 256
+    uint32_t first_mode = 1;  // Container::first_mode
     uint64_t seed = 1;
     int threads = 0;  // 0 = hardware concurrency
 };

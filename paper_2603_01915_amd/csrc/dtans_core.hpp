@@ -46,6 +46,12 @@ constexpr int kSlots = 4096;   // K
 constexpr int kMaxBase = 256;  // M
 constexpr int kWave = 64;      // lanes per wavefront (and per encoded wave)
 constexpr uint32_t kDeltaLimit = 1u << 30;  // table deltas are below this
+// First delta of a row (or of a lane that starts inside a row): the column
+// itself (the paper's choice, mode 0) or, in mode 1, the column minus the row
+// plus kFirstBias modulo 2^32, which a banded matrix keeps within the table
+// (the decoder starts such a row at row - kFirstBias and adds the delta).
+constexpr uint32_t kFirstBias = 1u << 29;
+DTANS_HD uint32_t first_base(uint32_t mode, uint32_t row) { return mode ? row - kFirstBias : 0u; }
 
 // unpack three words into the eight 12-bit slot indices i1..i8
 DTANS_HD void unpack8(uint32_t w1, uint32_t w2, uint32_t w3, uint32_t s[8]) {

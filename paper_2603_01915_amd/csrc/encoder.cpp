@@ -4,12 +4,13 @@
 // Decoding for Sparse MVM on GPUs" (2026):
 //  * column indices are delta-encoded per row; the first delta of a row (and,
 //    in the nonzero-balanced layout, of a lane stream) is the column itself
-//    (Sec. IV-A);
+//    (Sec. IV-A) or, in first-delta mode 1 (this library's default, not the
+//    paper's), the column relative to the row (dtans_core.hpp, kFirstBias);
 //  * every nonzero contributes a delta symbol followed by a value symbol; the
 //    lane streams of a 64-lane wave are interleaved word by word in the order
 //    the decoder's ballots consume them (Sec. IV-B);
 //  * each alphabet is fitted to K = 4096 slots with multiplicities at most
-//    M = 256 plus an escape symbol whose raw payload goes to a separate
+//    M = 256 (by default at most 255, see EncodeParams) plus an escape symbol whose raw payload goes to a separate
 //    region, minimising the expected size (Sec. IV-C, IV-F);
 //  * a forward base pass fixes the decoder's branches and a backward digit
 //    pass chooses slots and emits words (Sec. IV-E);
@@ -412,6 +413,7 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     c.n = n;
     c.nnz = nnz;
     c.seed = p.seed;
+    c.first_mode = p.first_mode;
     c.row_ptr.assign(row_ptr, row_ptr + m + 1);
     c.num_lanes = p.layout == kLayoutRow ? m : (nnz + p.lane_nnz - 1) / p.lane_nnz;
     c.num_waves = (c.num_lanes + kWave - 1) / kWave;
@@ -427,7 +429,12 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
             c.lane_range(l, g0, cnt);
             for (int64_t t = 0; t < cnt; ++t) {
                 int64_t g = g0 + t;
-                dkey[g] = (t == 0 || rowstart[g]) ? (uint64_t)col[g] : (uint64_t)(col[g] - col[g - 1]);
+                if (t == 0 || rowstart[g]) {
+                    const int64_t row = c.layout == kLayoutRow ? l : row_of(c.row_ptr, g);
+                    dkey[g] = (uint32_t)col[g] - first_base(c.first_mode, (uint32_t)row);
+                } else {
+                    dkey[g] = (uint64_t)(col[g] - col[g - 1]);
+                }
             }
         }
     });
@@ -625,6 +632,7 @@ std::string save_container(const Container &c, const std::string &path) {
                       (int64_t)c.escd.size(), (int64_t)c.escv.size()};
     memcpy(&b[24], h64, 64);
     memcpy(&b[88], &c.seed, 8);
+    memcpy(&b[104], &c.first_mode, 4);
     uint64_t chk = fnv1a(b.data() + kHeader, sz - kHeader);
     memcpy(&b[96], &chk, 8);
     FILE *f = fopen(path.c_str(), "wb");
@@ -663,7 +671,9 @@ std::string load_container(const std::string &path, Container &c) {
     c.m = h64[0]; c.n = h64[1]; c.nnz = h64[2]; c.num_lanes = h64[3]; c.num_waves = h64[4];
     const int64_t nw = h64[5], nd = h64[6], nv = h64[7];
     memcpy(&c.seed, &b[88], 8);
+    memcpy(&c.first_mode, &b[104], 4);
     if (c.dtype != kF32 && c.dtype != kF64) return fail("ECORRUPT", "bad dtype");
+    if (c.first_mode > 1) return fail("ECORRUPT", "bad first-delta mode");
     if (c.layout != kLayoutRow && c.layout != kLayoutNnz) return fail("ECORRUPT", "bad layout");
     if (c.m < 0 || c.n < 0 || c.nnz < 0 || nw < 0 || nd < 0 || nv < 0 || c.m >= (1ll << 31) ||
         c.n >= (1ll << 31) || c.nnz >= (1ll << 31))
@@ -791,7 +801,13 @@ std::string host_decode(const Container &c, int32_t *colout, uint64_t *valout) {
                             delta = c.escd[dp++];
                         }
                         int64_t g = g0[q] + t;
-                        uint64_t cc = (t == 0 || rowstart[g]) ? delta : (uint64_t)colv[q] + delta;
+                        uint64_t cc;
+                        if (t == 0 || rowstart[g]) {
+                            const int64_t row = c.layout == kLayoutRow ? w * kWave + q : row_of(c.row_ptr, g);
+                            cc = (uint32_t)(first_base(c.first_mode, (uint32_t)row) + (uint32_t)delta);
+                        } else {
+                            cc = (uint64_t)colv[q] + delta;
+                        }
                         if (cc >= (uint64_t)c.n) { err("column out of range"); break; }
                         colv[q] = (uint32_t)cc;
                         if (colout) colout[g] = (int32_t)cc;

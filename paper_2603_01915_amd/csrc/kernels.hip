@@ -513,7 +513,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         src.step_begin();
         src.consumed(pos);
     }
-    uint32_t d = 0, r = 1, col = 0;
+    uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row);
     int64_t g = g0;
     for (int j = 0; j < Smax; ++j) {
         const bool act = j < S;
@@ -620,7 +620,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                     row_end = n1.y;
                     n1 = n2;
                     n2 = a.nzr[min((int64_t)krow + 2, a.n_nzr)];
-                    col = 0;
+                    col = first_base(a.first_mode, (uint32_t)row);
                 }
                 col += dl[k];
                 cols[k] = col;
@@ -739,10 +739,12 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
 // heads of the following lanes) + beta * y.  One thread per split row sums a
-// short one (at most kLongSplit following lanes) by itself; a long one (a
-// power-law row can span thousands of lanes) is summed by the whole
-// wavefront, lanes striding over its partials, then a butterfly reduction.
-constexpr int kLongSplit = 8;
+// row spanning at most kLongSplit following lanes by itself (loads unrolled,
+// so several are in flight); a longer one (a power-law row can span
+// thousands of lanes) is summed by the whole wavefront, lanes striding over
+// its partials, then a butterfly reduction.  Such rows are rare, so a
+// wavefront taking them one after the other costs little.
+constexpr int kLongSplit = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -772,6 +774,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const int32_t *split_row, co
     if (valid && !longrow) {
         for (int c = 0; c < KC; ++c) {
             double sum = partial[(2 * (int64_t)a + 1) * KC + c];
+#pragma unroll 8
             for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
             put(row, c, sum);
         }

@@ -174,8 +174,43 @@ def test_info_statistics():
     assert inf["value_symbols"] <= 216 and inf["esc_value"] == 0
     assert 0 < inf["value_entropy"] <= np.log2(216) + 1e-9
     assert inf["value_cross_entropy"] >= inf["value_entropy"] - 1e-9
-    # the first delta of every row is its raw column (paper mode): escapes
-    assert inf["esc_delta"] > 0
+    # default first deltas relative to the row: a stencil's are a few offsets,
+    # all in the table; with the paper's raw columns most rows escape theirs
+    assert inf["first_delta_column"] == 0 and inf["esc_delta"] == 0
+    B = P.Matrix.from_csr(rp, ci, v, 16 ** 3, layout="row", first_delta_column=True)
+    infb = B.info()
+    assert infb["first_delta_column"] == 1 and infb["esc_delta"] > 0
+    assert inf["stream_bytes"] < infb["stream_bytes"]
+
+
+@pytest.mark.parametrize("layout,T", [("row", 0), ("nnz", 32), ("nnz", 12)])
+@pytest.mark.parametrize("first_column", [False, True])
+def test_first_delta_modes_cross_decode(tmp_path, layout, T, first_column):
+    """Both first-delta forms round-trip through the oracle's decoder and the
+    Python codec, with leading and inner empty rows, rows crossing lanes and
+    columns far from the diagonal (escaped first deltas in either mode)."""
+    rng = np.random.default_rng(5)
+    m, n = 400, 3000
+    rows = [[]] * 3 + [sorted(rng.choice(n, size=rng.integers(0, 20), replace=False))
+                       for _ in range(m - 6)] + [[], [n - 1], [0, 1, 2]]
+    rp = np.zeros(m + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], np.int32)
+    v = rng.choice(rng.standard_normal(40), len(ci))
+    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T, first_delta_column=first_column)
+    path = str(tmp_path / "m.dtans")
+    A.save(path)
+    assert oracle.read_header(path)["first_mode"] == (0 if first_column else 1)
+    r2, c2, v2 = oracle.decode(path)
+    assert np.array_equal(r2, rp) and np.array_equal(c2, ci) and np.array_equal(v2, v)
+    _, c3, v3 = container.decode(container.read(path))
+    assert np.array_equal(c3, ci) and np.array_equal(v3, v)
+    # and the oracle's encoder in the same mode is read back by the library
+    p2 = str(tmp_path / "o.dtans")
+    oracle.encode(p2, m, n, rp, ci, v, layout=1 if layout == "row" else 2, lane_nnz=T,
+                  first_mode=0 if first_column else 1)
+    B = P.Matrix.load(p2)
+    assert B.info()["first_delta_column"] == (1 if first_column else 0)
 
 
 def test_all_bases_256_word_count():
@@ -186,7 +221,8 @@ def test_all_bases_256_word_count():
     rows = [list(range(1, 4 * S + 1))] * m
     rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
     ci = np.array([c for r in rows for c in r], np.int32)
-    A = P.Matrix.from_csr(rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row", max_mult=256)
+    A = P.Matrix.from_csr(rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row", max_mult=256,
+                          first_delta_column=True)
     assert A.info()["words"] == m * (S + 2)
     assert A.info()["direct_table"] == 0
 
@@ -201,11 +237,12 @@ def test_multiplicity_cap():
     rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
     ci = np.array([c for r in rows for c in r], np.int32)
     v = np.ones(len(ci))
-    A = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row")
-    B = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row", max_mult=256)
+    kw = dict(layout="row", first_delta_column=True)  # one delta symbol
+    A = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, **kw)
+    B = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, max_mult=256, **kw)
     assert A.info()["direct_table"] == 1 and B.info()["direct_table"] == 0
     assert B.info()["words"] <= A.info()["words"] <= m * (S + 3)
-    C = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, layout="row", max_mult=16)
+    C = P.Matrix.from_csr(rp, ci, v, 4 * S + 1, max_mult=16, **kw)
     assert C.info()["words"] > A.info()["words"]
     for M in (A, B, C):
         import tempfile, os
