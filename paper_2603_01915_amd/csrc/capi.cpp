@@ -82,7 +82,7 @@ struct dtans_matrix {
     Container c;
     std::vector<uint64_t> gtab;
     std::vector<uint8_t> gval;
-    std::vector<int32_t> lane_row, split_row, split_first, split_last;
+    std::vector<int32_t> lane_row, split_row, split_first, split_last, split_long;
     std::vector<int32_t> nzr, empty_rows;  // layout NNZ: {row, end} pairs; rows without nonzeros
     DevBufs bufs;
     bool uploaded = false;
@@ -115,6 +115,15 @@ struct dtans_csr {
 };
 
 namespace {
+
+// split rows spanning more lanes than one thread should sum (the fix-up's
+// kLongSplit, 4 following lanes)
+std::vector<int32_t> long_splits(const std::vector<int32_t> &first, const std::vector<int32_t> &last) {
+    std::vector<int32_t> out;
+    for (size_t s = 0; s < first.size(); ++s)
+        if (last[s] - first[s] > 4) out.push_back((int32_t)s);
+    return out;
+}
 
 // Layout NNZ: the list of nonempty rows as {row, end} pairs with a {m, nnz}
 // sentinel, the rows without nonzeros, and lane_row rewritten from a row to
@@ -191,6 +200,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     const bool direct = gpu_table(c, h->gtab, h->gval);
     nnz_layout_meta(c, h->lane_row, h->split_row, h->split_first, h->split_last);
     nonempty_rows(c, h->lane_row, h->nzr, h->empty_rows);
+    h->split_long = long_splits(h->split_first, h->split_last);
     const bool f64 = c.dtype == kF64;
     const void *escv_src = c.escv.data();
     size_t escv_bytes = c.escv.size() * 8;
@@ -201,7 +211,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
         escv_src = escv32.data();
         escv_bytes = escv32.size() * 4;
     }
-    void *p[15];
+    void *p[16];
     HIP_TRY(h->bufs.upload(&p[0], h->gtab.data(), 8 * h->gtab.size(), st));
     HIP_TRY(h->bufs.upload(&p[1], h->gval.data(), h->gval.size(), st));
     HIP_TRY(h->bufs.upload(&p[2], c.row_ptr.data(), 4 * c.row_ptr.size(), st));
@@ -217,6 +227,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     HIP_TRY(h->bufs.upload(&p[12], h->split_last.data(), 4 * h->split_last.size(), st));
     HIP_TRY(h->bufs.upload(&p[13], h->nzr.data(), 4 * h->nzr.size(), st));
     HIP_TRY(h->bufs.upload(&p[14], h->empty_rows.data(), 4 * h->empty_rows.size(), st));
+    HIP_TRY(h->bufs.upload(&p[15], h->split_long.data(), 4 * h->split_long.size(), st));
     // the host staging vectors above must outlive the copies
     HIP_TRY(hipStreamSynchronize(st));
     DevMat &v = h->view;
@@ -234,15 +245,17 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.empty_rows = (const int32_t *)p[14];
     v.n_nzr = c.layout == kLayoutNnz ? (int64_t)h->nzr.size() / 2 - 1 : 0;
     v.n_empty = (int64_t)h->empty_rows.size();
-    v.split_row = (const int32_t *)p[10];
-    v.split_first = (const int32_t *)p[11];
-    v.split_last = (const int32_t *)p[12];
+    v.split.row = (const int32_t *)p[10];
+    v.split.first = (const int32_t *)p[11];
+    v.split.last = (const int32_t *)p[12];
+    v.split.longs = (const int32_t *)p[15];
+    v.split.n = (int64_t)h->split_row.size();
+    v.split.n_long = (int64_t)h->split_long.size();
     v.m = c.m;
     v.n = c.n;
     v.nnz = c.nnz;
     v.num_lanes = c.num_lanes;
     v.num_waves = c.num_waves;
-    v.nsplit = (int64_t)h->split_row.size();
     v.lane_nnz = (int32_t)c.lane_nnz;
     v.layout = (int32_t)c.layout;
     v.base_direct = direct ? 1 : 0;
@@ -812,7 +825,7 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
     while (G < 64 && G < mean) G <<= 1;
     c.group = G;
     c.lane_nnz = 32;
-    std::vector<int32_t> lane_row, split_row, split_first, split_last;
+    std::vector<int32_t> lane_row, split_row, split_first, split_last, split_long;
     if (variant == 2) {
         Container tmp;  // only row_ptr and the lane geometry are used
         tmp.layout = kLayoutNnz;
@@ -823,7 +836,7 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         tmp.row_ptr.assign(row_ptr, row_ptr + m + 1);
         nnz_layout_meta(tmp, lane_row, split_row, split_first, split_last);
         c.num_lanes = tmp.num_lanes;
-        c.nsplit = (int64_t)split_row.size();
+        split_long = long_splits(split_first, split_last);
     }
     std::vector<int32_t> blk;  // CSR-stream row blocks: <= 1024 nonzeros or one long row
     if (variant == 3) {
@@ -842,7 +855,7 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         }
         c.nblk = (int64_t)blk.size() - 1;
     }
-    void *p[8];
+    void *p[9];
     hipStream_t st = nullptr;
     hipError_t e;
     if ((e = h->bufs.upload(&p[7], blk.data(), 4 * blk.size(), st)) != hipSuccess ||
@@ -853,6 +866,7 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         (e = h->bufs.upload(&p[4], split_row.data(), 4 * split_row.size(), st)) != hipSuccess ||
         (e = h->bufs.upload(&p[5], split_first.data(), 4 * split_first.size(), st)) != hipSuccess ||
         (e = h->bufs.upload(&p[6], split_last.data(), 4 * split_last.size(), st)) != hipSuccess ||
+        (e = h->bufs.upload(&p[8], split_long.data(), 4 * split_long.size(), st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         delete h;
         return hip_err(e, "dtans_csr_create upload");
@@ -861,12 +875,15 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
     c.col = (const int32_t *)p[1];
     c.val = p[2];
     c.lane_row = (const int32_t *)p[3];
-    c.split_row = (const int32_t *)p[4];
-    c.split_first = (const int32_t *)p[5];
-    c.split_last = (const int32_t *)p[6];
+    c.split.row = (const int32_t *)p[4];
+    c.split.first = (const int32_t *)p[5];
+    c.split.last = (const int32_t *)p[6];
+    c.split.longs = (const int32_t *)p[8];
+    c.split.n = (int64_t)split_row.size();
+    c.split.n_long = (int64_t)split_long.size();
     c.blk = (const int32_t *)p[7];
     h->bytes = 4 * (m + 1) + nnz * (4 + (int64_t)vb) +
-               (variant == 2 ? 4 * c.num_lanes + 12 * c.nsplit : 0) +
+               (variant == 2 ? 4 * c.num_lanes + 12 * c.split.n : 0) +
                (variant == 3 ? 4 * (c.nblk + 1) : 0);
     *out = h;
     return DTANS_OK;

@@ -688,8 +688,39 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const int64_t s_end = (xcd_first + xcd_blocks) * wpb * a.num_waves / total;
     const int64_t stride = xcd_blocks * wpb;
     const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    for (int64_t s = s0; s < s_end; s += stride)
-        decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
+    if constexpr (LAYOUT == 2) {
+        // long lanes: a wave's start-up is a small part of its work
+        for (int64_t s = s0; s < s_end; s += stride)
+            decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
+        return;
+    }
+    // Row layout: the next encoded wave's lane geometry and stream bases are
+    // loaded while this one decodes, so a wave starts with one memory round
+    // trip (its first words) instead of two.
+    if (s0 >= s_end) return;
+    LaneGeo geo = lane_geo<LAYOUT>(a, s0, lane, lane_first_row<LAYOUT>(a, s0, lane));
+    int32_t fr1 = s0 + stride < s_end ? lane_first_row<LAYOUT>(a, s0 + stride, lane) : 0;
+    uint64_t wo = a.woff[s0], dof = a.doff[s0], vof = a.voff[s0];
+    for (int64_t s = s0; s < s_end; s += stride) {
+        const int64_t s1 = s + stride, s2 = s + 2 * stride;
+        const int32_t fr2 = s2 < s_end ? lane_first_row<LAYOUT>(a, s2, lane) : 0;
+        LaneGeo next{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0)};
+        uint64_t wo1 = 0, dof1 = 0, vof1 = 0;
+        if (s1 < s_end) {
+            next = lane_geo<LAYOUT>(a, s1, lane, fr1);
+            wo1 = a.woff[s1];
+            dof1 = a.doff[s1];
+            vof1 = a.voff[s1];
+        }
+        GlobalWords src{(const char *)(a.words + wo)};
+        Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
+        decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        geo = next;
+        fr1 = fr2;
+        wo = wo1;
+        dof = dof1;
+        vof = vof1;
+    }
 }
 
 // Same work as decode_kernel, with every wavefront owning one contiguous run
@@ -738,13 +769,13 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
 }
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
-// heads of the following lanes) + beta * y.  One thread per split row sums a
-// row spanning at most kLongSplit following lanes by itself (loads unrolled,
-// so several are in flight); a longer one (a power-law row can span
-// thousands of lanes) is summed by the whole wavefront, lanes striding over
-// its partials, then a butterfly reduction.  Such rows are rare, so a
-// wavefront taking them one after the other costs little.
-constexpr int kLongSplit = 64;
+// heads of the following lanes) + beta * y.  A row spanning at most
+// kLongSplit following lanes is summed by one thread (fixup_kernel); a longer
+// one by a whole wavefront (fixup_long_kernel, rows listed on the host): its
+// lanes stride over the row's partials, one running sum per column, then a
+// butterfly reduction per column.
+constexpr int kLongSplit = 4;
+constexpr int kMaxFixupCols = 32;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -753,44 +784,65 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename VT>
-__global__ __launch_bounds__(256) void fixup_kernel(const int32_t *split_row, const int32_t *first,
-                                                    const int32_t *last, int64_t nsplit,
-                                                    const double *partial, int KC, VT *Y,
-                                                    int64_t ldy, double alpha, double beta) {
+__device__ __forceinline__ void fixup_put(VT *Y, int64_t ldy, int32_t row, int c, double sum,
+                                          double alpha, double beta) {
+    VT *y = Y + (int64_t)row * ldy + c;
+    *y = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*y);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void fixup_kernel(SplitRows sr, const double *partial, int KC,
+                                                    VT *Y, int64_t ldy, double alpha, double beta) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= sr.n) return;
+    const int32_t a = sr.first[s], b = sr.last[s];
+    if (b - a > kLongSplit) return;
+    for (int c = 0; c < KC; ++c) {
+        double sum = partial[(2 * (int64_t)a + 1) * KC + c];
+        for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
+        fixup_put(Y, ldy, sr.row[s], c, sum, alpha, beta);
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void fixup_long_kernel(SplitRows sr, const double *partial, int KC,
+                                                         VT *Y, int64_t ldy, double alpha,
+                                                         double beta) {
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    const bool valid = s < nsplit;
-    int32_t a = 0, b = 0, row = 0;
-    if (valid) {
-        a = first[s];
-        b = last[s];
-        row = split_row[s];
+    if (w >= sr.n_long) return;  // whole wavefronts
+    const int64_t s = sr.longs[w];
+    const int32_t a = sr.first[s], b = sr.last[s];
+    double acc[kMaxFixupCols];
+#pragma unroll
+    for (int c = 0; c < kMaxFixupCols; ++c) acc[c] = 0.0;
+    for (int64_t l = (int64_t)a + lane; l <= b; l += kWave) {
+        const double *q = partial + (2 * l + (l == a ? 1 : 0)) * KC;  // tail of lane a, heads after
+#pragma unroll
+        for (int c = 0; c < kMaxFixupCols; ++c)
+            if (c < KC) acc[c] += q[c];
     }
-    const bool longrow = valid && b - a > kLongSplit;
-    auto put = [&](int32_t r, int c, double sum) {
-        VT *y = Y + (int64_t)r * ldy + c;
-        *y = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*y);
-    };
-    if (valid && !longrow) {
-        for (int c = 0; c < KC; ++c) {
-            double sum = partial[(2 * (int64_t)a + 1) * KC + c];
-#pragma unroll 8
-            for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
-            put(row, c, sum);
+#pragma unroll
+    for (int c = 0; c < kMaxFixupCols; ++c)
+        if (c < KC) {
+            const double sum = wave_sum(acc[c]);
+            if (lane == c) fixup_put(Y, ldy, sr.row[s], c, sum, alpha, beta);
         }
-    }
-    uint64_t lm = ballot(longrow);
-    while (lm) {  // wave-uniform
-        const int src = __builtin_ctzll(lm);
-        lm &= lm - 1;
-        const int32_t la = __shfl(a, src), lb = __shfl(b, src), lr = __shfl(row, src);
-        for (int c = 0; c < KC; ++c) {
-            double sum = lane == 0 ? partial[(2 * (int64_t)la + 1) * KC + c] : 0.0;
-            for (int64_t l = (int64_t)la + 1 + lane; l <= lb; l += kWave) sum += partial[(2 * l) * KC + c];
-            sum = wave_sum(sum);
-            if (lane == 0) put(lr, c, sum);
-        }
-    }
+}
+
+// both fix-up kernels for KC <= kMaxFixupCols columns of Y
+template <typename VT>
+hipError_t launch_fixup(const SplitRows &sr, const double *partial, int KC, VT *Y, int64_t ldy,
+                        double alpha, double beta, hipStream_t st) {
+    if (sr.n == 0) return hipSuccess;
+    if (KC > kMaxFixupCols) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((sr.n + 255) / 256)), dim3(256), 0, st, sr,
+                       partial, KC, Y, ldy, alpha, beta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sr.n_long == 0) return e;
+    hipLaunchKernelGGL(fixup_long_kernel<VT>, dim3((unsigned)((sr.n_long + 3) / 4)), dim3(256), 0, st,
+                       sr, partial, KC, Y, ldy, alpha, beta);
+    return hipGetLastError();
 }
 
 // Y[rows, :KC] = beta * Y (beta == 0: zero)
@@ -1049,13 +1101,8 @@ hipError_t for_kc(int k, int kcmax, F f) {
 template <typename VT>
 hipError_t nnz_epilogue(const DevMat &a, const double *partial, int KC, VT *Y, int64_t ldy,
                         double alpha, double beta, hipStream_t st) {
-    if (a.nsplit > 0) {
-        hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((a.nsplit + 255) / 256)), dim3(256), 0, st,
-                           a.split_row, a.split_first, a.split_last, a.nsplit, partial, KC, Y, ldy,
-                           alpha, beta);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = launch_fixup(a.split, partial, KC, Y, ldy, alpha, beta, st);
+    if (e != hipSuccess) return e;
     if (a.n_empty > 0) {
         const int64_t tot = a.n_empty * KC;
         hipLaunchKernelGGL(empty_rows_kernel<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
@@ -1234,11 +1281,8 @@ hipError_t csr_impl(const CsrDev &c, int k, const VT *X, int64_t ldx, VT *Y, int
             hipLaunchKernelGGL((csr_split_kernel<VT, KC>), dim3((unsigned)((c.num_lanes + 255) / 256)),
                                dim3(256), 0, st, c, X + c0, ldx, Y + c0, ldy, alpha, beta, partial);
             hipError_t e = hipGetLastError();
-            if (e != hipSuccess || c.nsplit == 0) return e;
-            hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((c.nsplit + 255) / 256)), dim3(256), 0,
-                               st, c.split_row, c.split_first, c.split_last, c.nsplit, partial, KC,
-                               Y + c0, ldy, alpha, beta);
-            return hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_fixup(c.split, partial, KC, Y + c0, ldy, alpha, beta, st);
         }
         const int64_t rows_per_block = 256 / c.group;
         int64_t blocks = (c.m + rows_per_block - 1) / rows_per_block;

@@ -6,6 +6,13 @@
 
 namespace dtans {
 
+// Rows split over lanes (nonzero-balanced layouts): row, first and last lane
+// of each; `longs` lists the ones spanning more than a few lanes.
+struct SplitRows {
+    const int32_t *row, *first, *last, *longs;
+    int64_t n, n_long;
+};
+
 // Device view of one encoded matrix (all pointers are device pointers).
 struct DevMat {
     const uint64_t *tab;     // K table entries (see dtans_core.hpp)
@@ -16,10 +23,10 @@ struct DevMat {
     const uint32_t *escd;
     const void *escv;        // raw escaped values (float or double)
     const int32_t *lane_row; // layout NNZ: index in nzr of the row of each lane's first nonzero
-    const int32_t *split_row, *split_first, *split_last;  // layout NNZ
+    SplitRows split;         // layout NNZ
     const int2 *nzr;         // layout NNZ: {row, end} of every nonempty row, then {m, nnz}
     const int32_t *empty_rows;  // layout NNZ: the rows without nonzeros
-    int64_t m, n, nnz, num_lanes, num_waves, nsplit;
+    int64_t m, n, nnz, num_lanes, num_waves;
     int64_t n_nzr, n_empty;    // layout NNZ: nonempty rows (nzr has n_nzr + 1 entries), empty rows
     int32_t lane_nnz, layout;  // layout: 1 row per lane, 2 nonzeros per lane
     int32_t base_direct;       // 1: table metadata holds bases, not bases - 1
@@ -81,9 +88,10 @@ hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, boo
 struct CsrDev {
     const int32_t *row_ptr, *col;
     const void *val;
-    const int32_t *lane_row, *split_row, *split_first, *split_last;
+    const int32_t *lane_row;
+    SplitRows split;
     const int32_t *blk;
-    int64_t m, n, nnz, num_lanes, nsplit, nblk;
+    int64_t m, n, nnz, num_lanes, nblk;
     int32_t variant, group, lane_nnz;
 };
 hipError_t launch_csr(const CsrDev &c, bool f64, int k, const void *X, int64_t ldx, void *Y,
