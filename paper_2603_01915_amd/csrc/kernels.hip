@@ -34,12 +34,6 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return v;
-}
-
 template <typename VT> struct Bits;
 template <> struct Bits<double> { typedef uint64_t T; };
 template <> struct Bits<float> { typedef uint32_t T; };
@@ -494,7 +488,6 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     int2 n1 = geo.n1, n2 = geo.n2;
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
     const int S = (cnt + 3) >> 2;
-    const int Smax = __builtin_amdgcn_readfirstlane(wave_max(S));  // uniform: scalar loop
 
     // stream offsets are 32-bit and wave-uniform (popcounts of ballots), so
     // they live in SGPRs
@@ -515,7 +508,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     }
     uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row);
     int64_t g = g0;
-    for (int j = 0; j < Smax; ++j) {
+    // the loop runs while some lane has a segment left (a uniform ballot test,
+    // no cross-lane reduction at the wave's start)
+    for (int j = 0; ballot(j < S) != 0; ++j) {
         const bool act = j < S;
         const bool more = j + 1 < S;
         const int rem = cnt - 4 * j;
@@ -531,7 +526,8 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         // while this segment's escapes and x gathers are served.  Every lane
         // issues the loads and selects the extracted word afterwards; lanes
         // that do not load read a neighbouring word of the stream.
-        if (j + 1 < Smax) {
+        const uint64_t m3 = ballot(more);  // lanes that load this step's words
+        if (m3) {
             uint32_t D, Rm1, x1, x2;
             auto group = [&](int q, uint32_t &x) {
                 const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
@@ -548,7 +544,6 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             const bool ext2 = group(4, x2);
             // masks combined on the scalar unit: a ballot of a plain compare
             // is the compare's own lane mask
-            const uint64_t m3 = ballot(more);
             const uint64_t m1 = m3 & ~ballot(ext1);
             const uint64_t m2 = m3 & ~ballot(ext2);
             const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
