@@ -61,7 +61,7 @@ typedef enum { DTANS_F32 = 1, DTANS_F64 = 2 } dtans_dtype;
  * summed by a fix-up pass.  AUTO lets the encoder choose. */
 typedef enum { DTANS_LAYOUT_AUTO = 0, DTANS_LAYOUT_ROW = 1, DTANS_LAYOUT_NNZ = 2 } dtans_layout;
 
-/* How SpMV (one right-hand side) reads its word streams (dtans_encode_opts). */
+/* How SpMV and SpMM read their word streams (dtans_encode_opts). */
 enum { DTANS_STAGE_AUTO = 0, DTANS_STAGE_DIRECT = 1, DTANS_STAGE_RING = 2 };
 
 typedef struct {
@@ -70,8 +70,9 @@ typedef struct {
     int32_t waves_per_wg;  /* kernel launch: wavefronts per workgroup (1..16); 0 = auto */
     int32_t wg_per_cu;     /* kernel launch: persistent workgroups per CU; 0 = auto */
     int32_t sort_rows;     /* 1: sort columns within rows first (values follow) */
-    int32_t stream_stage;  /* SpMV: 0 = auto (direct), 1 = read stream words directly
-                              from device memory, 2 = stage them through an LDS ring */
+    int32_t stream_stage;  /* SpMV/SpMM: 0 = auto (direct), 1 = read stream words
+                              directly from device memory, 2 = stage them through an
+                              LDS ring (SpMM then takes 2 FP64 / 4 FP32 columns per pass) */
     int32_t max_mult;      /* largest number of slots per symbol, 1..256 (Sec. IV-C's
                               cap M = 256); 0 = 255, which keeps every base within a
                               byte so that the kernels use it without a correction */
@@ -216,8 +217,8 @@ void dtans_csr_destroy(dtans_csr *csr);
  * around the automatic choice (multiples of 4 between 32 and 512); launch
  * shapes of the direct-read kernels (workgroups per CU up to the LDS limit,
  * waves per workgroup filling the CU's wave slots, then half and a quarter of
- * that); and for SpMV (k = 1) the LDS-ring stream stage with 16, 8 or 4 waves
- * per workgroup and as many workgroups per CU as fit.
+ * that); and the LDS-ring stream stage with 16, 8 or 4 waves per workgroup and
+ * as many workgroups per CU as fit.
  * Fields set in *in are kept in every candidate.
  *
  * dtans_autotune_candidates is host-only: it writes at most `cap` candidates,

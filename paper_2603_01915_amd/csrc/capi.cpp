@@ -179,11 +179,9 @@ Launch plan_launch(const dtans_matrix *h) {
     L.grid = (int)std::max<int64_t>(1, std::min(grid, need));
     L.num_cus = h->num_cus;
     L.ring = uses_ring(h) ? 1 : 0;
-    if (L.ring) {
-        // one 16-wave workgroup per CU; the launch adds as many as fit
-        L.waves_per_wg = h->waves_per_wg > 0 ? h->waves_per_wg : 16;
-        L.wg_per_cu = h->wg_per_cu;
-    }
+    // ring kernels: 16-wave workgroups unless set, as many per CU as fit
+    L.ring_waves_per_wg = h->waves_per_wg > 0 ? h->waves_per_wg : 16;
+    L.wg_per_cu = h->wg_per_cu;
     return L;
 }
 
@@ -406,13 +404,12 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
             c.stream_stage = stage;
             out.push_back(c);
         };
-        // SpMV: the direct-read shapes, then the LDS-ring kernels (their own
-        // shapes; workgroups per CU as many as fit unless fixed); products
-        // with several right-hand sides always read directly
-        if (o.stream_stage != DTANS_STAGE_RING || k > 1)
+        // the direct-read shapes, then the LDS-ring kernels (their own
+        // shapes; workgroups per CU as many as fit unless fixed)
+        if (o.stream_stage != DTANS_STAGE_RING)
             for (auto &w : launch_shapes(e.first, dtype == DTANS_F64, o.waves_per_wg, o.wg_per_cu))
-                push(w.first, w.second, k == 1 ? DTANS_STAGE_DIRECT : o.stream_stage);
-        if (k == 1 && o.stream_stage != DTANS_STAGE_DIRECT) {
+                push(w.first, w.second, DTANS_STAGE_DIRECT);
+        if (o.stream_stage != DTANS_STAGE_DIRECT) {
             if (o.waves_per_wg) push(o.waves_per_wg, o.wg_per_cu, DTANS_STAGE_RING);
             else
                 for (int w : {16, 8, 4}) push(w, o.wg_per_cu, DTANS_STAGE_RING);
@@ -580,7 +577,7 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->dtype = (int32_t)c.dtype;
     o->layout = (int32_t)c.layout;
     o->lane_nnz = (int32_t)c.lane_nnz;
-    o->waves_per_wg = plan_launch(mat).waves_per_wg;
+    o->waves_per_wg = uses_ring(mat) ? plan_launch(mat).ring_waves_per_wg : plan_launch(mat).waves_per_wg;
     o->num_lanes = c.num_lanes;
     o->num_waves = c.num_waves;
     o->words = (int64_t)c.words.size();

@@ -1149,46 +1149,66 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         if (e != hipSuccess || a.layout != 2) return e;
         return nnz_epilogue(a, partial, KC, Y + c0, ldy, alpha, beta, st);
     };
-    if (k == 1 && ldx == 1 && ldy == 1 && a.n * (int64_t)sizeof(VT) <= (1ll << 32)) {
-        if (L.ring) {
-            auto ring = [&](auto sinkc, auto kern) -> hipError_t {
-                typedef typename decltype(sinkc)::type SinkT;
-                typename SinkT::Params sp;
-                sp.X = X;
-                sp.ldx = 1;
-                sp.Y = Y;
-                sp.ldy = 1;
-                sp.partial = partial;
-                sp.alpha = alpha;
-                sp.beta = beta;
-                const size_t lds = (size_t)L.waves_per_wg * RingWords<kRingWords>::kWords * 4;
-                int per_cu = L.wg_per_cu;
-                if (per_cu <= 0) {
-                    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                    if (e != hipSuccess) return e;
-                    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)block.x, lds);
-                    if (e != hipSuccess) return e;
-                    per_cu = per_cu > 0 ? per_cu : 1;
-                }
-                const int64_t need = (a.num_waves + L.waves_per_wg - 1) / L.waves_per_wg;
-                const int grid =
-                    (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
-                hipLaunchKernelGGL(kern, dim3(grid), block, lds, st, a, sp);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess || a.layout != 2) return e;
-                return nnz_epilogue(a, partial, 1, Y, ldy, alpha, beta, st);
-            };
+    // LDS-ring kernels: deferred products, at most 2 (FP64) / 4 (FP32) columns
+    // per pass so that the deferred x values stay in registers
+    auto ring = [&](auto sinkc, auto kern, int KC, int c0) -> hipError_t {
+        typedef typename decltype(sinkc)::type SinkT;
+        typename SinkT::Params sp;
+        sp.X = X + c0;
+        sp.ldx = (uint32_t)ldx;
+        sp.Y = Y + c0;
+        sp.ldy = (uint32_t)ldy;
+        sp.partial = partial;
+        sp.alpha = alpha;
+        sp.beta = beta;
+        const int rw = L.ring_waves_per_wg;
+        const dim3 rblock(64 * rw);
+        const size_t lds = (size_t)rw * RingWords<kRingWords>::kWords * 4;
+        int per_cu = L.wg_per_cu;
+        if (per_cu <= 0) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)rblock.x, lds);
+            if (e != hipSuccess) return e;
+            per_cu = per_cu > 0 ? per_cu : 1;
+        }
+        const int64_t need = (a.num_waves + rw - 1) / rw;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.num_cus * per_cu, need));
+        hipLaunchKernelGGL(kern, dim3(grid), rblock, lds, st, a, sp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || a.layout != 2) return e;
+        return nnz_epilogue(a, partial, KC, Y + c0, ldy, alpha, beta, st);
+    };
+    const bool unit = k == 1 && ldx == 1 && ldy == 1 && a.n * (int64_t)sizeof(VT) <= (1ll << 32);
+    if (L.ring) {
+        if (unit) {
             typedef SpmmSink<VT, 1, true, double, 1> RowSink;
             typedef SpmmSink<VT, 1, true, double, 2> NnzSink;
             if (a.layout == 1)
                 return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, true>,
-                                                        ring_kernel<1, VT, RowSink, 4, false>));
+                                                        ring_kernel<1, VT, RowSink, 4, false>), 1, 0);
             return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, true>,
-                                                    ring_kernel<2, VT, NnzSink, 4, false>));
+                                                    ring_kernel<2, VT, NnzSink, 4, false>), 1, 0);
         }
-        return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
+        return for_kc(k, std::is_same<VT, double>::value ? 2 : 4, [&](auto KCc, int c0) {
+            constexpr int KC = decltype(KCc)::value;
+            if constexpr (KC > 4 || (std::is_same<VT, double>::value && KC > 2)) {
+                return hipErrorInvalidValue;  // excluded by the chunk limit
+            } else {
+                typedef SpmmSink<VT, KC, false, double, 1> RowSink;
+                typedef SpmmSink<VT, KC, false, double, 2> NnzSink;
+                if (a.layout == 1)
+                    return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, true>,
+                                                            ring_kernel<1, VT, RowSink, 4, false>),
+                                KC, c0);
+                return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, true>,
+                                                        ring_kernel<2, VT, NnzSink, 4, false>),
+                            KC, c0);
+            }
+        });
     }
+    if (unit) return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
     // widest column chunk that fits the registers without spilling
     const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
     const int kcmax = std::is_same<VT, double>::value ? 8 : 16;

@@ -36,7 +36,8 @@ struct DevMat {
 struct Launch {
     int waves_per_wg;   // 1..16
     int grid;           // number of workgroups (direct-read kernels)
-    int ring = 0;       // 1: SpMV of the row layout reads its streams through an LDS ring
+    int ring = 0;       // 1: SpMV/SpMM read their streams through an LDS ring
+    int ring_waves_per_wg = 16;  // ring kernels: wavefronts per workgroup
     int num_cus = 256;  // compute units of the device
     int wg_per_cu = 0;  // ring kernels: resident workgroups per CU (0: as many as fit)
 };

@@ -326,9 +326,9 @@ def test_autotune_candidates_small_and_fixed():
                               stream_stage=P.STAGE_DIRECT)
     assert c == [{"layout": P.LAYOUT_NNZ, "lane_nnz": 64, "waves_per_wg": 8, "wg_per_cu": 2,
                   "stream_stage": P.STAGE_DIRECT}]
-    # several right-hand sides: no ring candidates
+    # several right-hand sides: direct and ring candidates as for SpMV
     c = P.autotune_candidates(rp, len(ci), k=8)
-    assert c and all(o["stream_stage"] == 0 for o in c)
+    assert {o["stream_stage"] for o in c} == {P.STAGE_DIRECT, P.STAGE_RING}
     # empty matrix: one encoding, still valid shapes
     c = P.autotune_candidates(np.zeros(1, np.int32), 0)
     assert c and c[0]["layout"] == P.LAYOUT_NNZ
