@@ -34,6 +34,14 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// A load from a wave-uniform address through the scalar unit (constant
+// address space): the value lands in SGPRs.  Only for data no kernel of the
+// library writes while it runs (the matrix's offsets).
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 template <typename VT> struct Bits;
 template <> struct Bits<double> { typedef uint64_t T; };
 template <> struct Bits<float> { typedef uint32_t T; };
@@ -316,11 +324,26 @@ struct DecodeSink {
 // GlobalWords reads them from device memory: every step's loads depend on the
 // previous step's ballots, so each step waits for one memory round trip.
 struct GlobalWords {
-    const char *W;  // stream base of the current encoded wave
+    const char *W;   // stream base of the current encoded wave
+    // its length, kept in 64 bits: a narrower copy would leave half of the
+    // loaded offset unused, and reusing that register before the load has
+    // returned makes the wave wait for it
+    uint64_t bytes;
     // the word at byte offset pos (uniform) + 4 * (lanes of mask below this one)
     __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
         return *(const uint32_t *)(W + pos + 4 * lane_prefix(mask));
     }
+    // Nothing in the memory system fetches a stream ahead of its reads, so
+    // every step's words would come from HBM.  Once the first words are
+    // requested, one load per lane touches the next 64 cache lines (128 B)
+    // of the stream, which brings them into L2 while the first steps run.
+    // The value is kept (retire) so that the load is not removed; loads
+    // complete in order, so the steps' own waits already cover it.
+    __device__ __forceinline__ uint32_t prefetch(uint32_t pos, uint32_t lane) const {
+        const uint32_t o = (pos & ~127u) + 128u * (lane + 1);
+        return o < bytes ? *(const uint32_t *)(W + o) : 0u;
+    }
+    __device__ __forceinline__ void retire(uint32_t v) const { asm volatile("" ::"v"(v)); }
     __device__ __forceinline__ void step_begin() {}
     __device__ __forceinline__ void consumed(uint32_t) {}
 };
@@ -395,6 +418,8 @@ struct RingWords {
         const uint32_t *at = ring + (((pos + skew) >> 2) & (kRing - 1));
         return at[lane_prefix(mask)];
     }
+    __device__ __forceinline__ uint32_t prefetch(uint32_t, uint32_t) const { return 0u; }
+    __device__ __forceinline__ void retire(uint32_t) const {}
     __device__ __forceinline__ void step_begin() {
         if (has_pend) {
             write_chunk_part(pend_at, pend);
@@ -423,8 +448,9 @@ struct Cursor {
     const VT *EV;
 };
 
-// Where a lane's stream sits in the matrix: its first nonzero g0 and count;
-// the row of that nonzero with the row's [beg, end).  The nonzero layout
+// Where a lane's stream sits in the matrix: its first nonzero g0 and count
+// (the row layout keeps only the row's [beg, end)); the row of that nonzero
+// with the row's [beg, end).  The nonzero layout
 // walks the list of nonempty rows ({row, end} pairs, a sentinel {m, nnz} at
 // the end), so a lane never visits empty rows (their y is written by
 // empty_rows_kernel) and crosses exactly one row per nonzero that starts one;
@@ -451,23 +477,24 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
                                             int32_t first) {
     LaneGeo q{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0)};
     const int64_t l = slice * kWave + lane;
-    if (l < a.num_lanes) {
-        if (LAYOUT == 1) {
-            q.row = first;
-            q.row_beg = a.row_ptr[l];
-            q.cnt = a.row_ptr[l + 1] - q.row_beg;
-            q.g0 = q.row_beg;
-        } else {
-            q.g0 = l * (int64_t)a.lane_nnz;
-            q.cnt = (int)min((int64_t)a.lane_nnz, a.nnz - q.g0);
-            q.krow = first;
-            const int2 c = a.nzr[first];
-            q.row = c.x;
-            q.row_end = c.y;
-            q.row_beg = first > 0 ? a.nzr[first - 1].y : 0;
-            q.n1 = a.nzr[min((int64_t)first + 1, a.n_nzr)];
-            q.n2 = a.nzr[min((int64_t)first + 2, a.n_nzr)];
-        }
+    if constexpr (LAYOUT == 1) {
+        // the row's bounds only (lanes past the last row read the last
+        // row's): the count is formed where the wave starts, so that a wave
+        // loading the next one's geometry does not wait for it
+        const int64_t lc = l < a.num_lanes ? l : a.num_lanes - 1;
+        q.row = first;
+        q.row_beg = a.row_ptr[lc];
+        q.row_end = a.row_ptr[lc + 1];
+    } else if (l < a.num_lanes) {
+        q.g0 = l * (int64_t)a.lane_nnz;
+        q.cnt = (int)min((int64_t)a.lane_nnz, a.nnz - q.g0);
+        q.krow = first;
+        const int2 c = a.nzr[first];
+        q.row = c.x;
+        q.row_end = c.y;
+        q.row_beg = first > 0 ? a.nzr[first - 1].y : 0;
+        q.n1 = a.nzr[min((int64_t)first + 1, a.n_nzr)];
+        q.n2 = a.nzr[min((int64_t)first + 2, a.n_nzr)];
     }
     return q;
 }
@@ -482,8 +509,8 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                                              Src &src, Cursor<VT> &cur, const LaneGeo &geo) {
     const int64_t l = slice * kWave + lane;
     const bool live = l < a.num_lanes;
-    const int64_t g0 = geo.g0;
-    const int cnt = geo.cnt;
+    const int64_t g0 = LAYOUT == 1 ? (int64_t)geo.row_beg : geo.g0;
+    const int cnt = LAYOUT == 1 ? (live ? geo.row_end - geo.row_beg : 0) : geo.cnt;
     int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, krow = geo.krow;
     int2 n1 = geo.n1, n2 = geo.n2;
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
@@ -494,18 +521,24 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     uint32_t pos = cur.pos, dpos = cur.dpos, vpos = cur.vpos;
     const uint32_t *__restrict__ ED = cur.ED;
     const VT *__restrict__ EV = cur.EV;
-    uint32_t w1, w2, w3;
+    // A step's words: l1, l2 as loaded unless the check extracted them from
+    // the state (e1, e2; then x1, x2), l3 always loaded.  The selection is
+    // made at the top of the step that uses them, so that no instruction of
+    // the step that loads them waits for those loads.
+    uint32_t l1, l2, l3, x1 = 0, x2 = 0;
+    bool e1 = false, e2 = false;
     {
         // lanes without a stream read a neighbouring word (buffers are padded)
         const uint64_t mk = ballot(S > 0);
         const uint32_t c = 4 * (uint32_t)__popcll(mk);
-        w1 = src.read(pos, mk);
-        w2 = src.read(pos + c, mk);
-        w3 = src.read(pos + 2 * c, mk);
+        l1 = src.read(pos, mk);
+        l2 = src.read(pos + c, mk);
+        l3 = src.read(pos + 2 * c, mk);
         pos += 3 * c;
         src.step_begin();
         src.consumed(pos);
     }
+    const uint32_t pf = src.prefetch(pos, lane);
     uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row);
     int64_t g = g0;
     // the loop runs while some lane has a segment left (a uniform ballot test,
@@ -515,58 +548,20 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         const bool more = j + 1 < S;
         const int rem = cnt - 4 * j;
         uint32_t sl[8];
-        unpack8(w1, w2, w3, sl);
+        unpack8(e1 ? x1 : l1, e2 ? x2 : l2, l3, sl);
         uint64_t e[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) e[k] = tab[sl[k]];
         VT v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] = tval[sl[2 * k + 1]];
-        // The next segment's words first, so that their loads are in flight
-        // while this segment's escapes and x gathers are served.  Every lane
-        // issues the loads and selects the extracted word afterwards; lanes
-        // that do not load read a neighbouring word of the stream.
-        const uint64_t m3 = ballot(more);  // lanes that load this step's words
-        if (m3) {
-            uint32_t D, Rm1, x1, x2;
-            auto group = [&](int q, uint32_t &x) {
-                const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
-                const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
-                if constexpr (BD) {
-                    group4_direct(m0, m1, m2, m3, D, Rm1);
-                    return append_direct(d, r, D, Rm1, x);
-                } else {
-                    group4(m0, m1, m2, m3, D, Rm1);
-                    return append_and_check(d, r, D, Rm1, x);
-                }
-            };
-            const bool ext1 = group(0, x1);
-            const bool ext2 = group(4, x2);
-            // masks combined on the scalar unit: a ballot of a plain compare
-            // is the compare's own lane mask
-            const uint64_t m1 = m3 & ~ballot(ext1);
-            const uint64_t m2 = m3 & ~ballot(ext2);
-            const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
-            const uint32_t l1 = src.read(pos, m1);
-            const uint32_t l2 = src.read(pos + c1, m2);
-            const uint32_t l3 = src.read(pos + c1 + c2, m3);
-            pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
-            w1 = ext1 ? x1 : l1;
-            w2 = ext2 ? x2 : l2;
-            w3 = l3;
-        }
-        // deferred products of the previous step and the ring's pending chunk
-        // first, then this step's escapes (loaded and waited for at once),
-        // then the next chunk and this step's x loads, which the next step
-        // waits for: a step waits on memory for loads issued a step earlier
-        sink.pre_step();
-        src.step_begin();
-        // escape flags: bit 31 of a delta slot's entry, bit 30 of a value
-        // slot's entry.  When no active lane has either bit set in any of its
-        // eight entries (the common case) the low words are the deltas as they
-        // are; otherwise the flags are masked off and the escapes read.
-        // Padding symbols are never escapes, so only lanes past their last
-        // segment need masking.
+        // Escapes first (their loads are issued before the next words, so
+        // waiting for them does not wait for the words).  Escape flags: bit 31
+        // of a delta slot's entry, bit 30 of a value slot's entry.  When no
+        // active lane has either bit set in any of its eight entries (the
+        // common case) the low words are the deltas as they are; otherwise the
+        // flags are masked off and the escapes read.  Padding symbols are
+        // never escapes, so only lanes past their last segment need masking.
         uint32_t dl[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k];
@@ -590,6 +585,45 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                 vpos += (uint32_t)__popcll(mk);
             }
         }
+        // The next segment's words, in flight while this segment's x gathers
+        // are served.  The loads are issued on every step, so that the wait
+        // counts of the loads before them are the same on every path; lanes
+        // that do not load (all of them on a wave's last step) read a
+        // neighbouring word of the stream, whose value is not used.
+        const uint64_t m3 = ballot(more);  // lanes that load this step's words
+        uint64_t m1 = 0, m2 = 0;
+        if (m3) {
+            uint32_t D, R;
+            auto group = [&](int q, uint32_t &x) {
+                const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
+                const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
+                if constexpr (BD) {
+                    group4_direct(m0, m1, m2, m3, D, R);
+                    return append_direct(d, r, D, R, x);
+                } else {
+                    group4(m0, m1, m2, m3, D, R);
+                    return append_and_check(d, r, D, R, x);
+                }
+            };
+            e1 = group(0, x1);
+            e2 = group(4, x2);
+            // masks combined on the scalar unit: a ballot of a plain compare
+            // is the compare's own lane mask
+            m1 = m3 & ~ballot(e1);
+            m2 = m3 & ~ballot(e2);
+        }
+        {
+            const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
+            l1 = src.read(pos, m1);
+            l2 = src.read(pos + c1, m2);
+            l3 = src.read(pos + c1 + c2, m3);
+            pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
+        }
+        // deferred products of the previous step and the ring's pending chunk,
+        // then the next chunk and this step's x loads, which the next step
+        // waits for: a step waits on memory for loads issued a step earlier
+        sink.pre_step();
+        src.step_begin();
         src.consumed(pos);
         const int nreal = act ? min(rem, 4) : 0;
         uint32_t cols[4];
@@ -625,6 +659,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         }
         g += 4;
     }
+    src.retire(pf);
     cur.pos = pos;
     cur.dpos = dpos;
     cur.vpos = vpos;
@@ -644,8 +679,10 @@ template <int LAYOUT, typename VT, class Sink, bool BD>
 __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint64_t *tab,
                                                     const VT *tval, int64_t slice, uint32_t lane,
                                                     const typename Sink::Params &sp) {
-    GlobalWords src{(const char *)(a.words + a.woff[slice])};
-    Cursor<VT> cur{0, 0, 0, a.escd + a.doff[slice], (const VT *)a.escv + a.voff[slice]};
+    const uint64_t wo = uniform_load(a.woff + slice), we = uniform_load(a.woff + slice + 1);
+    GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
+    Cursor<VT> cur{0, 0, 0, a.escd + uniform_load(a.doff + slice),
+                   (const VT *)a.escv + uniform_load(a.voff + slice)};
     const LaneGeo geo = lane_geo<LAYOUT>(a, slice, lane, lane_first_row<LAYOUT>(a, slice, lane));
     decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, tab, tval, slice, lane, sp, src, cur, geo);
 }
@@ -692,27 +729,25 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     // Row layout: the next encoded wave's lane geometry and stream bases are
     // loaded while this one decodes, so a wave starts with one memory round
     // trip (its first words) instead of two.
+    // The loads for the next wave are issued on every pass (past the last
+    // wave they read this wave's again), so that no branch around them makes
+    // the wait counts of later loads unknown, which would turn the first
+    // wait of the wave into a wait for everything in flight.
     if (s0 >= s_end) return;
-    LaneGeo geo = lane_geo<LAYOUT>(a, s0, lane, lane_first_row<LAYOUT>(a, s0, lane));
-    int32_t fr1 = s0 + stride < s_end ? lane_first_row<LAYOUT>(a, s0 + stride, lane) : 0;
-    uint64_t wo = a.woff[s0], dof = a.doff[s0], vof = a.voff[s0];
+    LaneGeo geo = lane_geo<1>(a, s0, lane, lane_first_row<1>(a, s0, lane));
+    uint64_t wo = uniform_load(a.woff + s0), we = uniform_load(a.woff + s0 + 1);
+    uint64_t dof = uniform_load(a.doff + s0), vof = uniform_load(a.voff + s0);
     for (int64_t s = s0; s < s_end; s += stride) {
-        const int64_t s1 = s + stride, s2 = s + 2 * stride;
-        const int32_t fr2 = s2 < s_end ? lane_first_row<LAYOUT>(a, s2, lane) : 0;
-        LaneGeo next{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0)};
-        uint64_t wo1 = 0, dof1 = 0, vof1 = 0;
-        if (s1 < s_end) {
-            next = lane_geo<LAYOUT>(a, s1, lane, fr1);
-            wo1 = a.woff[s1];
-            dof1 = a.doff[s1];
-            vof1 = a.voff[s1];
-        }
-        GlobalWords src{(const char *)(a.words + wo)};
+        const int64_t s1 = s + stride < s_end ? s + stride : s;
+        const LaneGeo next = lane_geo<1>(a, s1, lane, lane_first_row<1>(a, s1, lane));
+        const uint64_t wo1 = uniform_load(a.woff + s1), we1 = uniform_load(a.woff + s1 + 1);
+        const uint64_t dof1 = uniform_load(a.doff + s1), vof1 = uniform_load(a.voff + s1);
+        GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
         Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
-        decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        decode_slice<1, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
         geo = next;
-        fr1 = fr2;
         wo = wo1;
+        we = we1;
         dof = dof1;
         vof = vof1;
     }
