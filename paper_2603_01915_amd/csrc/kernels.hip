@@ -687,14 +687,41 @@ __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint6
     decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, tab, tval, slice, lane, sp, src, cur, geo);
 }
 
+// Both tables into LDS in 16-byte pieces, every piece of a pass loaded before
+// any is stored, so that a pass costs one memory round trip (one pass for a
+// 1024-thread workgroup).
 template <typename VT>
 __device__ __forceinline__ void stage_tables(const DevMat &a, uint64_t *s_tab, VT *s_val) {
-    const VT *tv = (const VT *)a.tabval;
-    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
-        s_tab[i] = a.tab[i];
-        s_val[i] = tv[i];
+    constexpr int kT = kSlots * 8 / 16, kV = kSlots * (int)sizeof(VT) / 16;  // kV <= kT
+    const uint4 *gt = (const uint4 *)a.tab, *gv = (const uint4 *)a.tabval;
+    uint4 *lt = (uint4 *)s_tab, *lv = (uint4 *)s_val;
+    const int nt = blockDim.x;
+    for (int b = 0; b < kT; b += 2 * nt) {
+        const int i0 = b + (int)threadIdx.x, i1 = i0 + nt;
+        uint4 t0 = make_uint4(0, 0, 0, 0), t1 = t0, v0 = t0, v1 = t0;
+        if (i0 < kT) t0 = gt[i0];
+        if (i1 < kT) t1 = gt[i1];
+        if (i0 < kV) v0 = gv[i0];
+        if (i1 < kV) v1 = gv[i1];
+        if (i0 < kT) lt[i0] = t0;
+        if (i1 < kT) lt[i1] = t1;
+        if (i0 < kV) lv[i0] = v0;
+        if (i1 < kV) lv[i1] = v1;
     }
     __syncthreads();
+}
+
+// Wave priority from the share of a wavefront's encoded waves still ahead of
+// it (3 with more than three quarters left ... 0 in the last quarter).  The
+// arbiter otherwise favours the oldest wavefronts, which then finish their
+// (equal) shares early and leave the younger ones to end the launch at low
+// occupancy; ranking by remaining work keeps the wavefronts of a CU in step.
+__device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t total) {
+    const int64_t pr = total > 0 ? ((remaining - 1) * 4) / total : 0;
+    if (pr >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (pr == 2) __builtin_amdgcn_s_setprio(2);
+    else if (pr == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
 }
 
 // MINW: waves per SIMD the register allocation must allow (8 lets two
@@ -703,7 +730,6 @@ template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
 __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
-    stage_tables<VT>(a, s_tab, s_val);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t total = (int64_t)gridDim.x * wpb;
@@ -720,30 +746,38 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     const int64_t s_end = (xcd_first + xcd_blocks) * wpb * a.num_waves / total;
     const int64_t stride = xcd_blocks * wpb;
     const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t share = s0 < s_end ? (s_end - 1 - s0) / stride + 1 : 0;  // encoded waves of this wavefront
     if constexpr (LAYOUT == 2) {
+        stage_tables<VT>(a, s_tab, s_val);
         // long lanes: a wave's start-up is a small part of its work
-        for (int64_t s = s0; s < s_end; s += stride)
+        for (int64_t s = s0, k = 0; s < s_end; s += stride, ++k) {
+            set_progress_priority(share - k, share);
             decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
+        }
         return;
     }
     // Row layout: the next encoded wave's lane geometry and stream bases are
     // loaded while this one decodes, so a wave starts with one memory round
-    // trip (its first words) instead of two.
-    // The loads for the next wave are issued on every pass (past the last
-    // wave they read this wave's again), so that no branch around them makes
-    // the wait counts of later loads unknown, which would turn the first
-    // wait of the wave into a wait for everything in flight.
-    if (s0 >= s_end) return;
-    LaneGeo geo = lane_geo<1>(a, s0, lane, lane_first_row<1>(a, s0, lane));
-    uint64_t wo = uniform_load(a.woff + s0), we = uniform_load(a.woff + s0 + 1);
-    uint64_t dof = uniform_load(a.doff + s0), vof = uniform_load(a.voff + s0);
-    for (int64_t s = s0; s < s_end; s += stride) {
+    // trip (its first words) instead of two; the first wave's are requested
+    // before the tables are staged.  The loads for the next wave are issued
+    // on every pass (past the last wave they read this wave's again), so that
+    // no branch around them makes the wait counts of later loads unknown,
+    // which would turn the first wait of the wave into a wait for everything
+    // in flight.
+    const int64_t sf = s0 < s_end ? s0 : a.num_waves - 1;  // in bounds for idle wavefronts
+    LaneGeo geo = lane_geo<1>(a, sf, lane, lane_first_row<1>(a, sf, lane));
+    uint64_t wo = uniform_load(a.woff + sf), we = uniform_load(a.woff + sf + 1);
+    uint64_t dof = uniform_load(a.doff + sf), vof = uniform_load(a.voff + sf);
+    stage_tables<VT>(a, s_tab, s_val);
+    int64_t k = 0;
+    for (int64_t s = s0; s < s_end; s += stride, ++k) {
         const int64_t s1 = s + stride < s_end ? s + stride : s;
         const LaneGeo next = lane_geo<1>(a, s1, lane, lane_first_row<1>(a, s1, lane));
         const uint64_t wo1 = uniform_load(a.woff + s1), we1 = uniform_load(a.woff + s1 + 1);
         const uint64_t dof1 = uniform_load(a.doff + s1), vof1 = uniform_load(a.voff + s1);
         GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
         Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
+        set_progress_priority(share - k, share);
         decode_slice<1, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
         geo = next;
         wo = wo1;
