@@ -118,10 +118,11 @@ namespace {
 
 // split rows spanning more lanes than one thread should sum (the fix-up's
 // kLongSplit, 4 following lanes)
-std::vector<int32_t> long_splits(const std::vector<int32_t> &first, const std::vector<int32_t> &last) {
+std::vector<int32_t> long_splits(const std::vector<int32_t> &first, const std::vector<int32_t> &last,
+                                 int limit) {
     std::vector<int32_t> out;
     for (size_t s = 0; s < first.size(); ++s)
-        if (last[s] - first[s] > 4) out.push_back((int32_t)s);
+        if (last[s] - first[s] > limit) out.push_back((int32_t)s);
     return out;
 }
 
@@ -198,7 +199,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     const bool direct = gpu_table(c, h->gtab, h->gval);
     nnz_layout_meta(c, h->lane_row, h->split_row, h->split_first, h->split_last);
     nonempty_rows(c, h->lane_row, h->nzr, h->empty_rows);
-    h->split_long = long_splits(h->split_first, h->split_last);
+    h->split_long = long_splits(h->split_first, h->split_last, kLongSplitRuns);
     const bool f64 = c.dtype == kF64;
     const void *escv_src = c.escv.data();
     size_t escv_bytes = c.escv.size() * 8;
@@ -833,7 +834,7 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         tmp.row_ptr.assign(row_ptr, row_ptr + m + 1);
         nnz_layout_meta(tmp, lane_row, split_row, split_first, split_last);
         c.num_lanes = tmp.num_lanes;
-        split_long = long_splits(split_first, split_last);
+        split_long = long_splits(split_first, split_last, kLongSplit);
     }
     std::vector<int32_t> blk;  // CSR-stream row blocks: <= 1024 nonzeros or one long row
     if (variant == 3) {

@@ -25,7 +25,10 @@
 namespace dtans {
 namespace {
 
-constexpr int kComplete = 0, kHead = 1, kTail = 2;
+// How a lane holds a row: all of it; its end (the head: the row started in an
+// earlier lane); its start (the tail: it continues in later lanes); or, in
+// the nonzero layout, only a middle piece (started earlier, continues later).
+constexpr int kComplete = 0, kHead = 1, kTail = 2, kMid = 3;
 constexpr int kNumXcd = 8;
 constexpr int kRingWords = 1024;  // per-wavefront LDS ring of the ring kernels (4 KiB)
 
@@ -57,9 +60,12 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
 //     col[k] and values v[k]; nonzero k is number g + k in row-major order and
 //     lies in row rowk[k].  MULTI is false when a lane holds a single row.
 //     Every sink issues all its loads for the segment before it uses any.
-//   finish_row(row, kind): the lane has seen its last nonzero of `row`; kind
-//     says whether the lane holds the whole row, its head (the row started in
-//     an earlier lane) or its tail (the row continues in later lanes).
+//   finish_row(row, kind): row layout: the lane has seen its last nonzero of
+//     `row`, which it holds whole.
+//   finish_lane(row, kind, live): nonzero layout, called by every lane of the
+//     wavefront together at the end of an encoded wave; `row` holds the live
+//     lane's last nonzeros, `kind` how the lane holds it (kComplete, kHead,
+//     kTail or kMid).
 // Rows that end in the middle of a lane are finished inside segment().  Rows
 // without nonzeros are a lane of their own in the row layout (finish_row with
 // no segment) and never visited in the nonzero layout.
@@ -252,6 +258,34 @@ struct SpmmSink {
         consume();
         store(row, kind);
     }
+    // Middle pieces of a row are summed across the wavefront first: a
+    // segmented suffix sum over consecutive lanes holding middles of the same
+    // row (rows never decrease along the lanes, so equal rows d lanes apart
+    // mean the whole stretch holds that row), after which only the first
+    // such lane of each stretch stores (its head slot).  The fix-up then reads
+    // one partial per wavefront a row spans instead of one per lane.
+    __device__ __forceinline__ void finish_lane(int32_t row, int kind, bool live) {
+        consume();
+        const uint32_t wl = (uint32_t)lane & (kWave - 1);
+        const bool mid = live && kind == kMid;
+        const int32_t key = mid ? row : -1;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t kd = __shfl_down(key, d);
+            const bool ok = mid && wl + d < (uint32_t)kWave && kd == key;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const ACC t = __shfl_down(acc[c], d);
+                if (ok) acc[c] += t;
+            }
+        }
+        const int32_t kp = __shfl_up(key, 1);
+        if (mid) {
+            if (wl == 0 || kp != key) store(row, kHead);
+        } else if (live) {
+            store(row, kind);
+        }
+    }
 };
 
 // dX (k columns) += alpha * A^T dY, scattered with atomic adds.
@@ -291,6 +325,7 @@ struct TransSink {
     }
     __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
+    __device__ __forceinline__ void finish_lane(int32_t, int, bool) {}
 };
 
 // decode to CSR: column and value bits of every nonzero
@@ -315,6 +350,7 @@ struct DecodeSink {
     }
     __device__ __forceinline__ void pre_step() {}
     __device__ __forceinline__ void finish_row(int32_t, int) {}
+    __device__ __forceinline__ void finish_lane(int32_t, int, bool) {}
 };
 
 // --------------------------------------------------------- wave decoding
@@ -663,14 +699,15 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     cur.pos = pos;
     cur.dpos = dpos;
     cur.vpos = vpos;
-    if (!live) return;
-    if (LAYOUT == 1) {
-        if (l < a.m) sink.finish_row(row, kComplete);
+    if constexpr (LAYOUT == 1) {
+        if (live && l < a.m) sink.finish_row(row, kComplete);
     } else {
-        // `row` holds this lane's last nonzeros: complete when it ends here,
-        // else a tail (or, started in an earlier lane, a head) to be summed
+        // `row` holds this lane's last nonzeros: complete when it ends here;
+        // started in an earlier lane, a head when it ends here, else a
+        // middle; else a tail
         const int64_t gend = g0 + cnt;
-        sink.finish_row(row, row_beg < g0 ? kHead : (row_end <= gend ? kComplete : kTail));
+        const bool ends = row_end <= gend;
+        sink.finish_lane(row, row_beg < g0 ? (ends ? kHead : kMid) : (ends ? kComplete : kTail), live);
     }
 }
 
@@ -724,6 +761,44 @@ __device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t
     else __builtin_amdgcn_s_setprio(0);
 }
 
+// The row-layout sweep of decode_kernel over waves s0, s0 + stride, ... below
+// s_end (share of them).
+template <typename VT, class Sink, bool BD>
+__device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT *s_val,
+                                            uint32_t lane, const typename Sink::Params &sp,
+                                            int64_t s_end, int64_t s0, int64_t stride,
+                                            int64_t share) {
+    // Row layout: the next encoded wave's lane geometry and stream bases are
+    // loaded while this one decodes, so a wave starts with one memory round
+    // trip (its first words) instead of two; the first wave's are requested
+    // before the tables are staged.  The loads for the next wave are issued
+    // on every pass (past the last wave they read this wave's again), so that
+    // no branch around them makes the wait counts of later loads unknown,
+    // which would turn the first wait of the wave into a wait for everything
+    // in flight.
+    const int64_t sf = s0 < s_end ? s0 : a.num_waves - 1;  // in bounds for idle wavefronts
+    LaneGeo geo = lane_geo<1>(a, sf, lane, lane_first_row<1>(a, sf, lane));
+    uint64_t wo = uniform_load(a.woff + sf), we = uniform_load(a.woff + sf + 1);
+    uint64_t dof = uniform_load(a.doff + sf), vof = uniform_load(a.voff + sf);
+    stage_tables<VT>(a, s_tab, s_val);
+    int64_t k = 0;
+    for (int64_t s = s0; s < s_end; s += stride, ++k) {
+        const int64_t s1 = s + stride < s_end ? s + stride : s;
+        const LaneGeo next = lane_geo<1>(a, s1, lane, lane_first_row<1>(a, s1, lane));
+        const uint64_t wo1 = uniform_load(a.woff + s1), we1 = uniform_load(a.woff + s1 + 1);
+        const uint64_t dof1 = uniform_load(a.doff + s1), vof1 = uniform_load(a.voff + s1);
+        GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
+        Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
+        set_progress_priority(share - k, share);
+        decode_slice<1, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        geo = next;
+        wo = wo1;
+        we = we1;
+        dof = dof1;
+        vof = vof1;
+    }
+}
+
 // MINW: waves per SIMD the register allocation must allow (8 lets two
 // 16-wave workgroups share a CU, which is what the LDS tables permit)
 template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
@@ -754,36 +829,8 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
             set_progress_priority(share - k, share);
             decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
         }
-        return;
-    }
-    // Row layout: the next encoded wave's lane geometry and stream bases are
-    // loaded while this one decodes, so a wave starts with one memory round
-    // trip (its first words) instead of two; the first wave's are requested
-    // before the tables are staged.  The loads for the next wave are issued
-    // on every pass (past the last wave they read this wave's again), so that
-    // no branch around them makes the wait counts of later loads unknown,
-    // which would turn the first wait of the wave into a wait for everything
-    // in flight.
-    const int64_t sf = s0 < s_end ? s0 : a.num_waves - 1;  // in bounds for idle wavefronts
-    LaneGeo geo = lane_geo<1>(a, sf, lane, lane_first_row<1>(a, sf, lane));
-    uint64_t wo = uniform_load(a.woff + sf), we = uniform_load(a.woff + sf + 1);
-    uint64_t dof = uniform_load(a.doff + sf), vof = uniform_load(a.voff + sf);
-    stage_tables<VT>(a, s_tab, s_val);
-    int64_t k = 0;
-    for (int64_t s = s0; s < s_end; s += stride, ++k) {
-        const int64_t s1 = s + stride < s_end ? s + stride : s;
-        const LaneGeo next = lane_geo<1>(a, s1, lane, lane_first_row<1>(a, s1, lane));
-        const uint64_t wo1 = uniform_load(a.woff + s1), we1 = uniform_load(a.woff + s1 + 1);
-        const uint64_t dof1 = uniform_load(a.doff + s1), vof1 = uniform_load(a.voff + s1);
-        GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
-        Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
-        set_progress_priority(share - k, share);
-        decode_slice<1, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
-        geo = next;
-        wo = wo1;
-        we = we1;
-        dof = dof1;
-        vof = vof1;
+    } else {
+        decode_rows<VT, Sink, BD>(a, s_tab, s_val, lane, sp, s_end, s0, stride, share);
     }
 }
 
@@ -834,11 +881,10 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
 
 // rows split over lanes (layout NNZ): y = alpha * (tail of the first lane +
 // heads of the following lanes) + beta * y.  A row spanning at most
-// kLongSplit following lanes is summed by one thread (fixup_kernel); a longer
-// one by a whole wavefront (fixup_long_kernel, rows listed on the host): its
-// lanes stride over the row's partials, one running sum per column, then a
-// butterfly reduction per column.
-constexpr int kLongSplit = 4;
+// kLongSplit (kLongSplitRuns) following lanes is summed by one thread
+// (fixup_kernel); a longer one by a whole wavefront (fixup_long_kernel, rows
+// listed on the host): its lanes stride over the row's partials, one running
+// sum per column, then a butterfly reduction per column.
 constexpr int kMaxFixupCols = 32;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -854,23 +900,37 @@ __device__ __forceinline__ void fixup_put(VT *Y, int64_t ldy, int32_t row, int c
     *y = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*y);
 }
 
+// runs: the middle lanes' pieces were summed per wavefront (finish_lane), so
+// of the lanes strictly between the first (a) and the last (b) only the one
+// after the first and those starting a wavefront hold a partial; the first
+// wavefront start after a + 1:
+__device__ __forceinline__ int64_t first_run_start(int32_t a) { return ((int64_t)(a + 1) | (kWave - 1)) + 1; }
+
 template <typename VT>
 __global__ __launch_bounds__(256) void fixup_kernel(SplitRows sr, const double *partial, int KC,
-                                                    VT *Y, int64_t ldy, double alpha, double beta) {
+                                                    int runs, VT *Y, int64_t ldy, double alpha,
+                                                    double beta) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= sr.n) return;
     const int32_t a = sr.first[s], b = sr.last[s];
-    if (b - a > kLongSplit) return;
+    if (b - a > (runs ? kLongSplitRuns : kLongSplit)) return;
     for (int c = 0; c < KC; ++c) {
+        const double *head = partial + c;  // head slot of lane l: head[2 * l * KC]
         double sum = partial[(2 * (int64_t)a + 1) * KC + c];
-        for (int64_t l = a + 1; l <= b; ++l) sum += partial[(2 * l) * KC + c];
+        if (runs) {
+            sum += head[2 * (int64_t)(a + 1) * KC];
+            for (int64_t l = first_run_start(a); l < b; l += kWave) sum += head[2 * l * KC];
+            if (b > a + 1) sum += head[2 * (int64_t)b * KC];
+        } else {
+            for (int64_t l = a + 1; l <= b; ++l) sum += head[2 * l * KC];
+        }
         fixup_put(Y, ldy, sr.row[s], c, sum, alpha, beta);
     }
 }
 
 template <typename VT>
 __global__ __launch_bounds__(256) void fixup_long_kernel(SplitRows sr, const double *partial, int KC,
-                                                         VT *Y, int64_t ldy, double alpha,
+                                                         int runs, VT *Y, int64_t ldy, double alpha,
                                                          double beta) {
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -880,11 +940,24 @@ __global__ __launch_bounds__(256) void fixup_long_kernel(SplitRows sr, const dou
     double acc[kMaxFixupCols];
 #pragma unroll
     for (int c = 0; c < kMaxFixupCols; ++c) acc[c] = 0.0;
-    for (int64_t l = (int64_t)a + lane; l <= b; l += kWave) {
-        const double *q = partial + (2 * l + (l == a ? 1 : 0)) * KC;  // tail of lane a, heads after
+    auto add = [&](const double *q) {
 #pragma unroll
         for (int c = 0; c < kMaxFixupCols; ++c)
             if (c < KC) acc[c] += q[c];
+    };
+    if (runs) {
+        // lane 0: the tail of lane a and the head of lane a + 1; lane 1: the
+        // head of lane b; all lanes: the wavefront starts in between
+        if (lane == 0) {
+            add(partial + (2 * (int64_t)a + 1) * KC);
+            add(partial + 2 * (int64_t)(a + 1) * KC);
+        }
+        if (lane == 1) add(partial + 2 * (int64_t)b * KC);
+        for (int64_t l = first_run_start(a) + (int64_t)lane * kWave; l < b; l += (int64_t)kWave * kWave)
+            add(partial + 2 * l * KC);
+    } else {
+        for (int64_t l = (int64_t)a + lane; l <= b; l += kWave)
+            add(partial + (2 * l + (l == a ? 1 : 0)) * KC);  // tail of lane a, heads after
     }
 #pragma unroll
     for (int c = 0; c < kMaxFixupCols; ++c)
@@ -896,16 +969,16 @@ __global__ __launch_bounds__(256) void fixup_long_kernel(SplitRows sr, const dou
 
 // both fix-up kernels for KC <= kMaxFixupCols columns of Y
 template <typename VT>
-hipError_t launch_fixup(const SplitRows &sr, const double *partial, int KC, VT *Y, int64_t ldy,
-                        double alpha, double beta, hipStream_t st) {
+hipError_t launch_fixup(const SplitRows &sr, const double *partial, int KC, int runs, VT *Y,
+                        int64_t ldy, double alpha, double beta, hipStream_t st) {
     if (sr.n == 0) return hipSuccess;
     if (KC > kMaxFixupCols) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((sr.n + 255) / 256)), dim3(256), 0, st, sr,
-                       partial, KC, Y, ldy, alpha, beta);
+                       partial, KC, runs, Y, ldy, alpha, beta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sr.n_long == 0) return e;
     hipLaunchKernelGGL(fixup_long_kernel<VT>, dim3((unsigned)((sr.n_long + 3) / 4)), dim3(256), 0, st,
-                       sr, partial, KC, Y, ldy, alpha, beta);
+                       sr, partial, KC, runs, Y, ldy, alpha, beta);
     return hipGetLastError();
 }
 
@@ -1165,7 +1238,7 @@ hipError_t for_kc(int k, int kcmax, F f) {
 template <typename VT>
 hipError_t nnz_epilogue(const DevMat &a, const double *partial, int KC, VT *Y, int64_t ldy,
                         double alpha, double beta, hipStream_t st) {
-    hipError_t e = launch_fixup(a.split, partial, KC, Y, ldy, alpha, beta, st);
+    hipError_t e = launch_fixup(a.split, partial, KC, 1, Y, ldy, alpha, beta, st);
     if (e != hipSuccess) return e;
     if (a.n_empty > 0) {
         const int64_t tot = a.n_empty * KC;
@@ -1366,7 +1439,7 @@ hipError_t csr_impl(const CsrDev &c, int k, const VT *X, int64_t ldx, VT *Y, int
                                dim3(256), 0, st, c, X + c0, ldx, Y + c0, ldy, alpha, beta, partial);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            return launch_fixup(c.split, partial, KC, Y + c0, ldy, alpha, beta, st);
+            return launch_fixup(c.split, partial, KC, 0, Y + c0, ldy, alpha, beta, st);
         }
         const int64_t rows_per_block = 256 / c.group;
         int64_t blocks = (c.m + rows_per_block - 1) / rows_per_block;

@@ -7,7 +7,10 @@
 namespace dtans {
 
 // Rows split over lanes (nonzero-balanced layouts): row, first and last lane
-// of each; `longs` lists the ones spanning more than a few lanes.
+// of each; `longs` lists the ones summed by a whole wavefront: those spanning
+// more than kLongSplit lanes, or kLongSplitRuns when the middle lanes' pieces
+// were already summed per wavefront (the dtANS kernels).
+constexpr int kLongSplit = 4, kLongSplitRuns = 256;
 struct SplitRows {
     const int32_t *row, *first, *last, *longs;
     int64_t n, n_long;

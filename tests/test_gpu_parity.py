@@ -334,3 +334,44 @@ def test_launch_shapes_agree():
             ref = y
             check_spmv(y.cpu().numpy(), rp, ci, v, x.cpu().numpy(), None, 1.0, 0.0, np.float64)
         assert torch.equal(y, ref)
+
+
+def long_rows(T, seed=11):
+    """Rows spanning many lanes of T nonzeros: ends exactly at lane ends, one
+    lane past a wavefront boundary, several wavefronts, and more than 256
+    lanes (the wavefront-per-row fix-up), between short and empty rows."""
+    rng = np.random.default_rng(seed)
+    lens = [3, 64 * T - 3, T, 0, 2 * T, 65 * T + 1, 5, 300 * T + 7, 0, 0, 130 * T, 1, 64 * T, 17]
+    n = 20000
+    rows = [np.sort(rng.choice(n, size=min(L, n), replace=False)) if L <= n else
+            np.sort(rng.integers(0, n, size=L)) for L in lens]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    v = rng.choice([0.5, -1.25, 2.0, 3.0], size=len(ci))
+    return rp.astype(np.int32), ci, v, n
+
+
+@pytest.mark.parametrize("T", [32, 44, 128])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_long_split_rows(T, dtype):
+    """Rows split over many lanes: the middle lanes' pieces are summed per
+    wavefront before the fix-up; SpMV, SpMM and beta != 0 against the oracle."""
+    torch = need_gpu()
+    rp, ci, v, n = long_rows(T)
+    v = v.astype(dtype)
+    progress("long split rows T=%d %s" % (T, dtype.__name__))
+    A = P.Matrix.from_csr(rp, ci, v, n, layout="nnz", lane_nnz=T)
+    m = len(rp) - 1
+    x = workloads.vector(n, 7, dtype)
+    y0 = workloads.vector(m, 8, dtype)
+    y = torch.from_numpy(y0.copy()).cuda()
+    A.spmv(torch.from_numpy(x).cuda(), y, alpha=1.5, beta=-0.5)
+    check_spmv(y.cpu().numpy(), rp, ci, v, x, y0, 1.5, -0.5, dtype)
+    for k in (3, 8):
+        X = workloads.vector(n, 9, dtype, k=k)
+        Y = A.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+        Yref = oracle.spmm(rp, ci, v, X)
+        for c in range(k):
+            scale = oracle.absmv(rp, ci, v, X[:, c])
+            assert rel_error(Y[:, c], Yref[:, c], scale) <= TOL[dtype]
