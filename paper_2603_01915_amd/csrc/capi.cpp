@@ -301,12 +301,12 @@ int64_t sell_bytes(const Container &c, int slice) {
 // would be too few or badly balanced; for the nonzero layout enough lanes for
 // ~8 waves per SIMD of a 256-CU device, 32..512 nonzeros each.
 void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_encode_opts &o,
-                   int &layout, int &T) {
+                   bool f64, int &layout, int &T) {
     layout = o.layout;
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
+    const double mean = m ? (double)nnz / m : 0;
     if (layout == DTANS_LAYOUT_AUTO) {
-        int64_t maxlen = 0;
-        for (int64_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, row_ptr[i + 1] - row_ptr[i]);
-        double mean = m ? (double)nnz / m : 0;
         int64_t waves = (m + 63) / 64;
         layout = (waves < 2048 || maxlen > 8 * std::max(mean, 4.0)) ? DTANS_LAYOUT_NNZ : DTANS_LAYOUT_ROW;
     }
@@ -314,8 +314,19 @@ void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_e
     if (layout == DTANS_LAYOUT_NNZ) {
         T = o.lane_nnz;
         if (T == 0) {
-            int64_t lanes_target = 256LL * 4 * 8 * 64;
-            int64_t t = nnz / std::max<int64_t>(1, lanes_target);
+            int64_t t;
+            if (maxlen <= 4 * std::max(mean, 1.0)) {
+                // regular rows: encoded waves cost about the same, so give
+                // every wavefront the SpMV launch keeps resident (256 CUs,
+                // 27 (FP32) or 28 (FP64) per CU) exactly one of them: a
+                // second, partial round would double the time of a share
+                const int64_t resident = 256LL * (f64 ? 28 : 27);
+                t = (nnz + 64 * resident - 1) / (64 * resident);
+            } else {
+                // irregular rows: the cost of a wave varies with its rows,
+                // several per wavefront even it out
+                t = nnz / (256LL * 4 * 8 * 64);
+            }
             T = (int)std::min<int64_t>(512, std::max<int64_t>(32, (t + 3) / 4 * 4));
         }
     }
@@ -366,7 +377,7 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
     // encodings: the automatic choice first, then the other layout, then
     // neighbouring lane lengths (x1/2, x2, x1/4, x4 of the automatic one)
     int auto_layout = 0, auto_T = 0;
-    auto_encoding(m, nnz, row_ptr, o, auto_layout, auto_T);
+    auto_encoding(m, nnz, row_ptr, o, dtype == DTANS_F64, auto_layout, auto_T);
     std::vector<std::pair<int, int>> enc{{auto_layout, auto_T}};
     auto add = [&](int lay, int T) {
         for (auto &e : enc)
@@ -377,7 +388,7 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
         dtans_encode_opts nn = o;
         nn.layout = DTANS_LAYOUT_NNZ;
         int lay = 0, T0 = 0;
-        auto_encoding(m, nnz, row_ptr, nn, lay, T0);
+        auto_encoding(m, nnz, row_ptr, nn, dtype == DTANS_F64, lay, T0);
         add(DTANS_LAYOUT_ROW, 0);
         add(DTANS_LAYOUT_NNZ, T0);
     }
@@ -386,7 +397,7 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
         dtans_encode_opts nn = o;
         nn.layout = DTANS_LAYOUT_NNZ;
         int lay = 0, T0 = 0;
-        auto_encoding(m, nnz, row_ptr, nn, lay, T0);
+        auto_encoding(m, nnz, row_ptr, nn, dtype == DTANS_F64, lay, T0);
         for (int f : {-2, 2, -4, 4}) {
             int T = f > 0 ? T0 * f : T0 / -f;
             T = std::min(512, std::max(32, (T + 3) / 4 * 4));
@@ -515,7 +526,7 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     p.max_mult = o.max_mult ? (uint32_t)o.max_mult : 255u;
     p.first_mode = o.first_delta_column ? 0u : 1u;
     int layout = 0, T = 0;
-    auto_encoding(m, nnz, row_ptr, o, layout, T);
+    auto_encoding(m, nnz, row_ptr, o, dtype == DTANS_F64, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
     if (p.layout == kLayoutNnz) p.lane_nnz = (uint32_t)T;
     dtans_matrix *h = new dtans_matrix();
