@@ -200,7 +200,7 @@ struct SpmmSink {
                 return;
             }
         }
-        if (KC <= 4) {
+        if (KC * sizeof(VT) <= 32) {  // all four rows of X in flight at once
             VT x[4][KC];
             if (nreal >= 4 && (!MULTI || rowk[3] == cur)) {  // common case: no tail, no row end
 #pragma unroll
@@ -229,7 +229,7 @@ struct SpmmSink {
                     for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)v[k], (ACC)x[k][c], acc[c]);
                 }
         } else {
-            // wide rows of X: load nonzero k+1 while multiplying nonzero k
+            // wider rows of X: load nonzero k+1 while multiplying nonzero k
             VT xa[KC], xb[KC];
             if (nreal > 0) {
 #pragma unroll
