@@ -258,6 +258,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.lane_nnz = (int32_t)c.lane_nnz;
     v.layout = (int32_t)c.layout;
     v.base_direct = direct ? 1 : 0;
+    v.no_escape = c.dtab.has_escape || c.vtab.has_escape ? 0 : 1;
     v.first_mode = c.first_mode;
     h->device = dev;
     h->num_cus = device_cus(dev);

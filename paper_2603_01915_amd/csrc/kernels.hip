@@ -537,8 +537,10 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
 
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
 // nonzeros of this thread's lane to a sink constructed here.
-// BD: "direct" tables (every base at most 255, stored as is; see dtans_core.hpp)
-template <int LAYOUT, typename VT, class Sink, class Src, bool BD>
+// TF, the table format: 0 bases stored minus one (see dtans_core.hpp); 1
+// "direct" tables (every base at most 255, stored as is); 2 direct tables
+// without an escape symbol in either alphabet (no escape checks at all)
+template <int LAYOUT, typename VT, class Sink, class Src, int TF>
 __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
                                              const VT *__restrict__ tval, int64_t slice,
                                              uint32_t lane, const typename Sink::Params &sp,
@@ -603,7 +605,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k];
         const uint32_t flags = (uint32_t)e[0] | (uint32_t)e[1] | (uint32_t)e[2] | (uint32_t)e[3] |
                                (uint32_t)e[4] | (uint32_t)e[5] | (uint32_t)e[6] | (uint32_t)e[7];
-        if (ballot(act) & ballot(flags >= kDeltaLimit)) {  // uniform
+        if (TF != 2 && (ballot(act) & ballot(flags >= kDeltaLimit))) {  // uniform
 #pragma unroll
             for (int k = 0; k < 4; ++k) dl[k] &= kDeltaLimit - 1;
 #pragma unroll
@@ -633,7 +635,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             auto group = [&](int q, uint32_t &x) {
                 const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
                 const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
-                if constexpr (BD) {
+                if constexpr (TF >= 1) {
                     group4_direct(m0, m1, m2, m3, D, R);
                     return append_direct(d, r, D, R, x);
                 } else {
@@ -712,7 +714,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
 }
 
 // one encoded wave read straight from device memory
-template <int LAYOUT, typename VT, class Sink, bool BD>
+template <int LAYOUT, typename VT, class Sink, int TF>
 __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint64_t *tab,
                                                     const VT *tval, int64_t slice, uint32_t lane,
                                                     const typename Sink::Params &sp) {
@@ -721,7 +723,7 @@ __device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint6
     Cursor<VT> cur{0, 0, 0, a.escd + uniform_load(a.doff + slice),
                    (const VT *)a.escv + uniform_load(a.voff + slice)};
     const LaneGeo geo = lane_geo<LAYOUT>(a, slice, lane, lane_first_row<LAYOUT>(a, slice, lane));
-    decode_slice<LAYOUT, VT, Sink, GlobalWords, BD>(a, tab, tval, slice, lane, sp, src, cur, geo);
+    decode_slice<LAYOUT, VT, Sink, GlobalWords, TF>(a, tab, tval, slice, lane, sp, src, cur, geo);
 }
 
 // Both tables into LDS in 16-byte pieces, every piece of a pass loaded before
@@ -763,7 +765,7 @@ __device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t
 
 // The row-layout sweep of decode_kernel over waves s0, s0 + stride, ... below
 // s_end (share of them).
-template <typename VT, class Sink, bool BD>
+template <typename VT, class Sink, int TF>
 __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT *s_val,
                                             uint32_t lane, const typename Sink::Params &sp,
                                             int64_t s_end, int64_t s0, int64_t stride,
@@ -790,7 +792,7 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
         GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
         Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
         set_progress_priority(share - k, share);
-        decode_slice<1, VT, Sink, GlobalWords, BD>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        decode_slice<1, VT, Sink, GlobalWords, TF>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
         geo = next;
         wo = wo1;
         we = we1;
@@ -801,7 +803,7 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
 
 // MINW: waves per SIMD the register allocation must allow (8 lets two
 // 16-wave workgroups share a CU, which is what the LDS tables permit)
-template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
+template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
 __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
@@ -827,10 +829,10 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
         // long lanes: a wave's start-up is a small part of its work
         for (int64_t s = s0, k = 0; s < s_end; s += stride, ++k) {
             set_progress_priority(share - k, share);
-            decode_slice_global<LAYOUT, VT, Sink, BD>(a, s_tab, s_val, s, lane, sp);
+            decode_slice_global<LAYOUT, VT, Sink, TF>(a, s_tab, s_val, s, lane, sp);
         }
     } else {
-        decode_rows<VT, Sink, BD>(a, s_tab, s_val, lane, sp, s_end, s0, stride, share);
+        decode_rows<VT, Sink, TF>(a, s_tab, s_val, lane, sp, s_end, s0, stride, share);
     }
 }
 
@@ -839,7 +841,7 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
 // them through an LDS ring (RingWords).  The XCD shares are those of
 // decode_kernel; inside a share the runs are consecutive, which keeps the
 // rows an XCD works on within a window of its share.
-template <int LAYOUT, typename VT, class Sink, int MINW, bool BD>
+template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
 __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ uint64_t s_tab[kSlots];
     __shared__ VT s_val[kSlots];
@@ -872,7 +874,7 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
         const int32_t fr2 = s + 2 < sb ? lane_first_row<LAYOUT>(a, s + 2, lane) : 0;
         LaneGeo next{0, 0, 0, 0, 0, 0};
         if (s + 1 < sb) next = lane_geo<LAYOUT>(a, s + 1, lane, fr1);
-        decode_slice<LAYOUT, VT, Sink, RingWords<kRingWords>, BD>(a, s_tab, s_val, s, lane, sp, src, cur,
+        decode_slice<LAYOUT, VT, Sink, RingWords<kRingWords>, TF>(a, s_tab, s_val, s, lane, sp, src, cur,
                                                                  geo);
         geo = next;
         fr1 = fr2;
@@ -1043,10 +1045,10 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         sp.beta = beta;
         for (int w = wib; w < task.num_waves; w += wpb)
             if (a.base_direct)
-                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, true>(a, s_tab, s_val,
+                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, 1>(a, s_tab, s_val,
                                                                         task.first_wave + w, lane, sp);
             else
-                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, false>(a, s_tab, s_val,
+                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, 0>(a, s_tab, s_val,
                                                                          task.first_wave + w, lane, sp);
     }
 }
@@ -1254,6 +1256,10 @@ template <typename K>
 K pick_bd(const DevMat &a, K direct, K general) {
     return a.base_direct ? direct : general;
 }
+template <typename K>
+K pick_tf(const DevMat &a, K direct_noesc, K direct, K general) {
+    return a.base_direct ? (a.no_escape ? direct_noesc : direct) : general;
+}
 
 template <typename VT>
 hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, int64_t ldy,
@@ -1280,12 +1286,12 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         sp.alpha = alpha;
         sp.beta = beta;
         if (a.layout == 1)
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, SinkT, SinkT::kOcc, true>,
-                                       decode_kernel<1, VT, SinkT, SinkT::kOcc, false>),
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, SinkT, SinkT::kOcc, 1>,
+                                       decode_kernel<1, VT, SinkT, SinkT::kOcc, 0>),
                                dim3(L.grid), block, 0, st, a, sp);
         else
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), true>,
-                                       decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), false>),
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 1>,
+                                       decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 0>),
                                dim3(L.grid), block, 0, st, a, sp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || a.layout != 2) return e;
@@ -1328,10 +1334,10 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
             typedef SpmmSink<VT, 1, true, double, 1> RowSink;
             typedef SpmmSink<VT, 1, true, double, 2> NnzSink;
             if (a.layout == 1)
-                return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, true>,
-                                                        ring_kernel<1, VT, RowSink, 4, false>), 1, 0);
-            return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, true>,
-                                                    ring_kernel<2, VT, NnzSink, 4, false>), 1, 0);
+                return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, 1>,
+                                                        ring_kernel<1, VT, RowSink, 4, 0>), 1, 0);
+            return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, 1>,
+                                                    ring_kernel<2, VT, NnzSink, 4, 0>), 1, 0);
         }
         return for_kc(k, std::is_same<VT, double>::value ? 2 : 4, [&](auto KCc, int c0) {
             constexpr int KC = decltype(KCc)::value;
@@ -1341,16 +1347,39 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
                 typedef SpmmSink<VT, KC, false, double, 1> RowSink;
                 typedef SpmmSink<VT, KC, false, double, 2> NnzSink;
                 if (a.layout == 1)
-                    return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, true>,
-                                                            ring_kernel<1, VT, RowSink, 4, false>),
+                    return ring(TypeBox<RowSink>(), pick_bd(a, ring_kernel<1, VT, RowSink, 4, 1>,
+                                                            ring_kernel<1, VT, RowSink, 4, 0>),
                                 KC, c0);
-                return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, true>,
-                                                        ring_kernel<2, VT, NnzSink, 4, false>),
+                return ring(TypeBox<NnzSink>(), pick_bd(a, ring_kernel<2, VT, NnzSink, 4, 1>,
+                                                        ring_kernel<2, VT, NnzSink, 4, 0>),
                             KC, c0);
             }
         });
     }
-    if (unit) return launch(TypeBox<SpmmSink<VT, 1, true>>(), 1, 0);
+    if (unit) {
+        // single vectors also have instances without escape handling
+        typedef SpmmSink<VT, 1, true> SinkT;
+        typename SinkT::Params sp;
+        sp.X = X;
+        sp.ldx = 1;
+        sp.Y = Y;
+        sp.ldy = 1;
+        sp.partial = partial;
+        sp.alpha = alpha;
+        sp.beta = beta;
+        constexpr int occ = SinkT::kOcc, occn = occ_nnz(SinkT::kOcc);
+        if (a.layout == 1)
+            hipLaunchKernelGGL(pick_tf(a, decode_kernel<1, VT, SinkT, occ, 2>, decode_kernel<1, VT, SinkT, occ, 1>,
+                                       decode_kernel<1, VT, SinkT, occ, 0>),
+                               dim3(L.grid), block, 0, st, a, sp);
+        else
+            hipLaunchKernelGGL(pick_tf(a, decode_kernel<2, VT, SinkT, occn, 2>, decode_kernel<2, VT, SinkT, occn, 1>,
+                                       decode_kernel<2, VT, SinkT, occn, 0>),
+                               dim3(L.grid), block, 0, st, a, sp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || a.layout != 2) return e;
+        return nnz_epilogue(a, partial, 1, Y, ldy, alpha, beta, st);
+    }
     // widest column chunk that fits the registers without spilling
     const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
     const int kcmax = std::is_same<VT, double>::value ? 8 : 16;
@@ -1386,13 +1415,13 @@ hipError_t spmm_t_impl(const DevMat &a, int k, const VT *dY, int64_t lddy, VT *d
         sp.alpha = alpha;
         const dim3 block(64 * L.waves_per_wg);
         if (a.layout == 1)
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, true>,
-                                       decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, false>),
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, 1>,
+                                       decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, 0>),
                                dim3(L.grid), block, 0,
                                st, a, sp);
         else
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), true>,
-                                       decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), false>),
+            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), 1>,
+                                       decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), 0>),
                                dim3(L.grid), block, 0,
                                st, a, sp);
         return hipGetLastError();
@@ -1407,12 +1436,12 @@ hipError_t decode_impl(const DevMat &a, int32_t *col, void *vals, Launch L, hipS
     sp.vals = (typename Bits<VT>::T *)vals;
     const dim3 block(64 * L.waves_per_wg);
     if (a.layout == 1)
-        hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, true>,
-                                   decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, false>),
+        hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, 1>,
+                                   decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, 0>),
                            dim3(L.grid), block, 0, st, a, sp);
     else
-        hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), true>,
-                                   decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), false>),
+        hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), 1>,
+                                   decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), 0>),
                            dim3(L.grid), block, 0, st, a, sp);
     return hipGetLastError();
 }

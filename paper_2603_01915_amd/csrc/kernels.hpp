@@ -33,6 +33,7 @@ struct DevMat {
     int64_t n_nzr, n_empty;    // layout NNZ: nonempty rows (nzr has n_nzr + 1 entries), empty rows
     int32_t lane_nnz, layout;  // layout: 1 row per lane, 2 nonzeros per lane
     int32_t base_direct;       // 1: table metadata holds bases, not bases - 1
+    int32_t no_escape;         // 1: neither table holds the escape symbol
     uint32_t first_mode;       // first delta of a row: 0 its column, 1 relative to the row
 };
 
