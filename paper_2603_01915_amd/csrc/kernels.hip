@@ -202,7 +202,9 @@ struct SpmmSink {
         }
         if (KC * sizeof(VT) <= 32) {  // all four rows of X in flight at once
             VT x[4][KC];
-            if (nreal >= 4 && (!MULTI || rowk[3] == cur)) {  // common case: no tail, no row end
+            // common case, taken by the whole wavefront or not at all (a
+            // uniform branch): no lane has a tail or a row end here
+            if (!ballot(!(nreal >= 4 && (!MULTI || rowk[3] == cur)))) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -365,9 +367,13 @@ struct GlobalWords {
     // loaded offset unused, and reusing that register before the load has
     // returned makes the wave wait for it
     uint64_t bytes;
-    // the word at byte offset pos (uniform) + 4 * (lanes of mask below this one)
+    // the word at byte offset pos (uniform) + 4 * (lanes of mask below this one):
+    // the base stays fixed in SGPRs and each lane forms its 32-bit offset with
+    // one shift-add (readfirstlane keeps pos a scalar sum, which the compiler
+    // would otherwise fold into the lane count)
     __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
-        return *(const uint32_t *)(W + pos + 4 * lane_prefix(mask));
+        const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
+        return *(const uint32_t *)(W + (p + 4 * lane_prefix(mask)));
     }
     // Nothing in the memory system fetches a stream ahead of its reads, so
     // every step's words would come from HBM.  Once the first words are
