@@ -174,6 +174,8 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "batch":
+        return bench_batch(args, torch, P)
     log("generating workload %s" % args.workload)
     W = make_workload(args.workload)
     rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
@@ -278,6 +280,87 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_batch(args, torch, P):
+    """64 banded FP32 matrices of 1k-64k rows (8-64 nonzeros per row) in one
+    persistent launch, against the plain CSR kernel launched per matrix."""
+    import workloads
+
+    log("generating 64 uneven matrices")
+    mats_csr = workloads.batch()
+    total_nnz = sum(len(c[1]) for _, c in mats_csr)
+    log("encoding %d matrices, %d nonzeros" % (len(mats_csr), total_nnz))
+    t0 = time.perf_counter()
+    enc = [P.Matrix.from_csr(c[0], c[1], c[2], m, layout="row") for m, c in mats_csr]
+    enc_s = time.perf_counter() - t0
+    dt_bytes = sum(A.info()["total_bytes"] for A in enc)
+    csr_bytes = sum(A.info()["csr_bytes"] for A in enc)
+    vec_bytes = sum(2 * m * 4 for m, _ in mats_csr)
+    copies = args.copies or max(1, math.ceil(2 * MALL_BYTES / (dt_bytes + vec_bytes)))
+    sets = [enc]
+    if copies > 1:
+        import tempfile
+
+        with tempfile.TemporaryDirectory() as td:
+            paths = []
+            for i, A in enumerate(enc):
+                paths.append(os.path.join(td, "a%d.dtans" % i))
+                A.save(paths[-1])
+            for _ in range(copies - 1):
+                sets.append([P.Matrix.load(q) for q in paths])
+    for S in sets:
+        for A in S:
+            A.to_device()
+    batches = [P.Batch(S) for S in sets]
+    gen = torch.Generator(device="cuda").manual_seed(2005)
+    xs = [[torch.rand(m, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
+          for _ in range(copies)]
+    ys = [[torch.empty(m, dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(copies)]
+
+    def step(i):
+        j = i % copies
+        batches[j].spmv(xs[j], ys[j])
+
+    log("timing %d steps over %d copies" % (args.steps, copies))
+    ms, _ = time_steps(torch, step, args.steps, args.warmup)
+    flops = 2.0 * total_nnz
+    alg = dt_bytes + vec_bytes
+    res = {
+        "metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "batch of 64 banded fp32 matrices, 1k-64k rows, 8-64 nnz/row, one launch",
+                   "matrices": len(mats_csr), "nnz": total_nnz, "k": 1, "layout": "row",
+                   "copies_rotated": copies},
+        "compressed_GBps": round(alg / (ms * 1e-3) / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": alg},
+        "compression": {"dtans_bytes": dt_bytes, "csr_bytes": csr_bytes,
+                        "ratio_vs_csr": round(csr_bytes / dt_bytes, 3)},
+        "encode_seconds": round(enc_s, 2),
+    }
+    if not args.no_csr:
+        log("plain CSR baseline, one launch per matrix")
+        ccopies = max(1, math.ceil(2 * MALL_BYTES / (csr_bytes + vec_bytes)))
+        cs = [[P.CsrBaseline(c[0], c[1], c[2], m) for m, c in mats_csr] for _ in range(ccopies)]
+        cx = [[torch.rand(m, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
+              for _ in range(ccopies)]
+        cy = [[torch.empty(m, dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(ccopies)]
+
+        def cstep(i):
+            j = i % ccopies
+            for B, x, y in zip(cs[j], cx[j], cy[j]):
+                B.spmv(x, y)
+
+        cms, _ = time_steps(torch, cstep, args.steps, args.warmup)
+        res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),
+                               "copies_rotated": ccopies, "launches_per_step": len(mats_csr)}
+        res["speedup_vs_csr"] = round(cms / ms, 3)
     print(json.dumps(res), flush=True)
     return 0
 

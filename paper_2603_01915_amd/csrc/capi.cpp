@@ -163,16 +163,37 @@ bool uses_ring(const dtans_matrix *h) {
     return h->stage == DTANS_STAGE_RING && 4 * (int64_t)h->c.words.size() < (1ll << 31);
 }
 
-Launch plan_launch(const dtans_matrix *h) {
-    const bool f64 = h->c.dtype == kF64;
+// Default workgroup shape of the decode kernels: LDS admits 160 KiB /
+// table_bytes workgroups per CU (2 for FP64, 3 for FP32); the registers admit
+// `per_simd` waves per SIMD (8 for the row-layout SpMV kernels, 7 for the
+// nonzero-balanced ones).  A workgroup's waves are dealt to the CU's 4 SIMDs,
+// so its size is kept a multiple of 4: with 9-wave workgroups, three per CU
+// did not all fit at 7 per SIMD and the third started only when another
+// ended.  Among workgroup counts, the most resident waves win (then the most
+// workgroups).
+void default_shape(bool f64, int per_simd, int &wpw, int &wgcu) {
     const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
-    const int lds_per_cu = 160 * 1024;
-    // LDS admits lds_per_cu / table_bytes workgroups per CU (2 for FP64, 3 for
-    // FP32).  The row-layout SpMV kernels fit 8 waves per SIMD (32 per CU),
-    // the nonzero-balanced ones 7 (28 per CU); split those slots evenly.
-    int wgcu = h->wg_per_cu > 0 ? h->wg_per_cu : std::max(1, lds_per_cu / table_bytes);
-    const int slots = h->c.layout == kLayoutRow ? 32 : 28;
-    int wpw = h->waves_per_wg > 0 ? h->waves_per_wg : std::min(16, slots / wgcu);
+    const int maxwg = std::max(1, 160 * 1024 / table_bytes);
+    wpw = 4;
+    wgcu = 1;
+    for (int g = maxwg; g >= 1; --g) {
+        const int w = std::min(16, (4 * per_simd / g) & ~3);
+        if (w >= 4 && w * g > wpw * wgcu) {
+            wpw = w;
+            wgcu = g;
+        }
+    }
+}
+
+Launch plan_launch(const dtans_matrix *h) {
+    const int per_simd = h->c.layout == kLayoutRow ? 8 : 7;
+    int wpw = 0, wgcu = 0;
+    default_shape(h->c.dtype == kF64, per_simd, wpw, wgcu);
+    if (h->wg_per_cu > 0) {
+        wgcu = h->wg_per_cu;
+        wpw = std::max(4, std::min(16, (4 * per_simd / wgcu) & ~3));
+    }
+    if (h->waves_per_wg > 0) wpw = h->waves_per_wg;
     Launch L;
     L.waves_per_wg = wpw;
     int64_t need = (h->c.num_waves + wpw - 1) / wpw;
@@ -318,10 +339,12 @@ void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_e
             int64_t t;
             if (maxlen <= 4 * std::max(mean, 1.0)) {
                 // regular rows: encoded waves cost about the same, so give
-                // every wavefront the SpMV launch keeps resident (256 CUs,
-                // 27 (FP32) or 28 (FP64) per CU) exactly one of them: a
-                // second, partial round would double the time of a share
-                const int64_t resident = 256LL * (f64 ? 28 : 27);
+                // every wavefront the SpMV launch keeps resident exactly one
+                // of them: a second, partial round would double the time of
+                // a share
+                int wpw = 0, wgcu = 0;
+                default_shape(f64, 7, wpw, wgcu);
+                const int64_t resident = 256LL * wpw * wgcu;
                 t = (nnz + 64 * resident - 1) / (64 * resident);
             } else {
                 // irregular rows: the cost of a wave varies with its rows,
@@ -338,20 +361,30 @@ void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_e
 std::vector<std::pair<int, int>> launch_shapes(int layout, bool f64, int wpw_fixed, int wg_fixed) {
     const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
     const int maxwg = std::max(1, 160 * 1024 / table_bytes);
-    const int slots = layout == DTANS_LAYOUT_ROW ? 32 : 28;
+    const int per_simd = layout == DTANS_LAYOUT_ROW ? 8 : 7;
     std::vector<std::pair<int, int>> out;  // (waves_per_wg, wg_per_cu)
     std::vector<int> wgs;
-    if (wg_fixed) wgs.push_back(wg_fixed);
-    else
-        for (int g = maxwg; g >= 1; --g) wgs.push_back(g);
+    if (wg_fixed) {
+        wgs.push_back(wg_fixed);
+    } else {
+        // the library's own shape first
+        int dw = 0, dg = 0;
+        default_shape(f64, per_simd, dw, dg);
+        if (!wpw_fixed) out.push_back({dw, dg});
+        wgs.push_back(dg);
+        for (int g = maxwg; g >= 1; --g)
+            if (g != dg) wgs.push_back(g);
+    }
     for (int g : wgs) {
-        const int base = std::min(16, std::max(1, slots / g));
+        // waves dealt evenly to the 4 SIMDs (see default_shape)
+        const int base = std::min(16, std::max(4, (4 * per_simd / g) & ~3));
         std::vector<int> ws;
         if (wpw_fixed) ws.push_back(wpw_fixed);
         else
             for (int w : {base, base / 2, base / 4})
                 if (w >= 2 && std::find(ws.begin(), ws.end(), w) == ws.end()) ws.push_back(w);
-        for (int w : ws) out.push_back({w, g});
+        for (int w : ws)
+            if (std::find(out.begin(), out.end(), std::make_pair(w, g)) == out.end()) out.push_back({w, g});
     }
     return out;
 }
@@ -726,10 +759,8 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
             cost.push_back((double)(c.word_off[w + 1] - c.word_off[w]) + 256.0);
         }
     }
-    const bool f64tab = f64;
-    const int table_bytes = kSlots * (8 + (f64tab ? 8 : 4));
-    const int wgcu = std::max(1, 160 * 1024 / table_bytes);
-    const int wpw = f64tab ? 14 : 9;
+    int wpw = 0, wgcu = 0;
+    default_shape(f64, 7, wpw, wgcu);  // batch_kernel allows 7 waves per SIMD
     const int64_t total_waves = (int64_t)wmat.size();
     int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)mats[0]->num_cus * wgcu,
                                                            (total_waves + wpw - 1) / wpw));

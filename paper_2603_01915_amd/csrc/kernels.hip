@@ -771,11 +771,14 @@ __device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t
 
 // The row-layout sweep of decode_kernel over waves s0, s0 + stride, ... below
 // s_end (share of them).
+// stage: 0 the tables are in LDS already; 1 stage them; 2 wait for the
+// workgroup (its previous matrix), then stage them (the whole workgroup
+// passes the same value).
 template <typename VT, class Sink, int TF>
 __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT *s_val,
                                             uint32_t lane, const typename Sink::Params &sp,
                                             int64_t s_end, int64_t s0, int64_t stride,
-                                            int64_t share) {
+                                            int64_t share, int stage = 1) {
     // Row layout: the next encoded wave's lane geometry and stream bases are
     // loaded while this one decodes, so a wave starts with one memory round
     // trip (its first words) instead of two; the first wave's are requested
@@ -788,7 +791,8 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
     LaneGeo geo = lane_geo<1>(a, sf, lane, lane_first_row<1>(a, sf, lane));
     uint64_t wo = uniform_load(a.woff + sf), we = uniform_load(a.woff + sf + 1);
     uint64_t dof = uniform_load(a.doff + sf), vof = uniform_load(a.voff + sf);
-    stage_tables<VT>(a, s_tab, s_val);
+    if (stage == 2) __syncthreads();
+    if (stage) stage_tables<VT>(a, s_tab, s_val);
     int64_t k = 0;
     for (int64_t s = s0; s < s_end; s += stride, ++k) {
         const int64_t s1 = s + stride < s_end ? s + stride : s;
@@ -1031,16 +1035,9 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
     for (int t = t0; t < t1; ++t) {
         const BatchTask task = b.tasks[t];
         const DevMat a = b.mats[task.mat];  // uniform: scalar loads into SGPRs
-        if (task.mat != cur) {  // restage the tables only when the matrix changes
-            __syncthreads();
-            const VT *tv = (const VT *)a.tabval;
-            for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
-                s_tab[i] = a.tab[i];
-                s_val[i] = tv[i];
-            }
-            __syncthreads();
-            cur = task.mat;
-        }
+        // the tables are restaged only when the matrix changes
+        const int stage = task.mat == cur ? 0 : (cur < 0 ? 1 : 2);
+        cur = task.mat;
         typename SpmmSink<VT, 1, true>::Params sp;
         sp.X = (const VT *)b.ptrs[2 * task.mat];
         sp.ldx = 1;
@@ -1049,13 +1046,15 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         sp.partial = nullptr;
         sp.alpha = alpha;
         sp.beta = beta;
-        for (int w = wib; w < task.num_waves; w += wpb)
-            if (a.base_direct)
-                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, 1>(a, s_tab, s_val,
-                                                                        task.first_wave + w, lane, sp);
-            else
-                decode_slice_global<1, VT, SpmmSink<VT, 1, true>, 0>(a, s_tab, s_val,
-                                                                         task.first_wave + w, lane, sp);
+        // this wavefront's waves of the task: first_wave + wib, + wpb, ...
+        const int64_t s0 = task.first_wave + wib, s_end = (int64_t)task.first_wave + task.num_waves;
+        const int64_t share = s0 < s_end ? (s_end - 1 - s0) / wpb + 1 : 0;
+        if (a.base_direct)
+            decode_rows<VT, SpmmSink<VT, 1, true>, 1>(a, s_tab, s_val, lane, sp, s_end, s0, wpb, share,
+                                                       stage);
+        else
+            decode_rows<VT, SpmmSink<VT, 1, true>, 0>(a, s_tab, s_val, lane, sp, s_end, s0, wpb, share,
+                                                       stage);
     }
 }
 

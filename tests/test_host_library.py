@@ -290,7 +290,8 @@ def test_autotune_candidates_regular(dtype):
     assert info["waves_per_wg"] == c[0]["waves_per_wg"]
     assert info["stream_stage"] == P.STAGE_DIRECT
     maxwg = 2 if dtype == np.float64 else 3
-    assert c[0]["wg_per_cu"] == maxwg
+    # the library's shape: two 16-wave workgroups (8 waves per SIMD)
+    assert (c[0]["waves_per_wg"], c[0]["wg_per_cu"]) == (16, 2)
     keys = [tuple(o.values()) for o in c]
     assert len(set(keys)) == len(keys)
     Ts = sorted({o["lane_nnz"] for o in c if o["layout"] == P.LAYOUT_NNZ})
