@@ -176,6 +176,8 @@ def main():
         del src, dst
     if args.workload == "batch":
         return bench_batch(args, torch, P)
+    if args.workload == "autograd":
+        return bench_autograd(args, torch, P)
     log("generating workload %s" % args.workload)
     W = make_workload(args.workload)
     rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
@@ -280,6 +282,93 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_autograd(args, torch, P):
+    """The differentiable product on the pruned 11008 x 4096 weight with a
+    batch of 16: one step is the forward Y = A X and the backward
+    dX = A^T dY (decode-and-scatter), through DtansLinearFn.  The plain CSR
+    baseline runs the forward on A and the backward on an explicitly
+    transposed CSR copy of A."""
+    import scipy.sparse as sp
+
+    from paper_2603_01915_amd.autograd import DtansLinearFn
+    import workloads
+
+    rp, ci, v = workloads.pruned_weight()
+    m, n, k, nnz = len(rp) - 1, 4096, 16, len(ci)
+    log("encoding %d x %d, %d nonzeros" % (m, n, nnz))
+    t0 = time.perf_counter()
+    A0 = P.Matrix.from_csr(rp, ci, v, n)
+    enc_s = time.perf_counter() - t0
+    info = A0.info()
+    vec_bytes = 2 * (n + m) * k * 4
+    copies = args.copies or max(1, math.ceil(2 * MALL_BYTES / (info["total_bytes"] + vec_bytes)))
+    mats = [A0]
+    if copies > 1:
+        import tempfile
+
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "a.dtans")
+            A0.save(path)
+            mats += [P.Matrix.load(path) for _ in range(copies - 1)]
+    for A in mats:
+        A.to_device()
+    gen = torch.Generator(device="cuda").manual_seed(2005)
+    Xs = [(torch.rand((n, k), dtype=torch.float32, device="cuda", generator=gen) * 2 - 1).requires_grad_()
+          for _ in range(copies)]
+    dYs = [torch.rand((m, k), dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for _ in range(copies)]
+
+    def step(i):
+        j = i % copies
+        Y = DtansLinearFn.apply(mats[j], Xs[j])
+        Y.backward(dYs[j])
+
+    log("timing %d steps over %d copies" % (args.steps, copies))
+    ms, _ = time_steps(torch, step, args.steps, args.warmup)
+    flops = 2 * 2.0 * nnz * k
+    alg = 2 * info["total_bytes"] + vec_bytes
+    res = {
+        "metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "autograd pruned 11008x4096 fp32, batch 16, forward + backward",
+                   "rows": m, "cols": n, "nnz": nnz, "k": k, "layout": {1: "row", 2: "nnz"}[info["layout"]],
+                   "lane_nnz": info["lane_nnz"], "copies_rotated": copies},
+        "compressed_GBps": round(alg / (ms * 1e-3) / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": alg},
+        "compression": {"dtans_bytes": info["total_bytes"], "csr_bytes": info["csr_bytes"],
+                        "ratio_vs_csr": round(info["csr_bytes"] / info["total_bytes"], 3)},
+        "encode_seconds": round(enc_s, 2),
+    }
+    if not args.no_csr:
+        log("plain CSR baseline: forward on A, backward on A^T")
+        At = sp.csr_matrix((v, ci, rp), shape=(m, n)).T.tocsr()
+        At.sort_indices()
+        rpt, cit, vt = At.indptr.astype(np.int32), At.indices.astype(np.int32), At.data.astype(np.float32)
+        B, Bt = P.CsrBaseline(rp, ci, v, n), P.CsrBaseline(rpt, cit, vt, m)
+        ccopies = max(1, math.ceil(2 * MALL_BYTES / (2 * B.bytes + vec_bytes)))
+        pairs = [(B, Bt)] + [(P.CsrBaseline(rp, ci, v, n), P.CsrBaseline(rpt, cit, vt, m))
+                             for _ in range(ccopies - 1)]
+        cX = [torch.rand((n, k), dtype=torch.float32, device="cuda", generator=gen) for _ in range(ccopies)]
+        cdY = [torch.rand((m, k), dtype=torch.float32, device="cuda", generator=gen) for _ in range(ccopies)]
+        cY = [torch.empty((m, k), dtype=torch.float32, device="cuda") for _ in range(ccopies)]
+        cdX = [torch.empty((n, k), dtype=torch.float32, device="cuda") for _ in range(ccopies)]
+
+        def cstep(i):
+            j = i % ccopies
+            pairs[j][0].spmm(cX[j], cY[j])
+            pairs[j][1].spmm(cdY[j], cdX[j])
+
+        cms, _ = time_steps(torch, cstep, args.steps, args.warmup)
+        res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),
+                               "copies_rotated": ccopies}
+        res["speedup_vs_csr"] = round(cms / ms, 3)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -27,7 +27,9 @@
  *   - Indices are 32-bit (Sec. V: int32 CSR); nnz, rows and columns must be
  *     below 2^31.
  *   - A handle is used by one thread at a time; calls on different handles
- *     may run concurrently.
+ *     may run concurrently.  A handle's device scratch (partial sums of the
+ *     nonzero layout, the transposed product's copies of dX) is shared by its
+ *     calls, so calls on one handle that may use it are ordered on one stream.
  */
 #ifndef DTANS_H
 #define DTANS_H
@@ -159,8 +161,12 @@ dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx
 
 /*
  * Transposed product dX = alpha * A^T dY + beta * dX by decode-and-scatter of
- * the same streams (atomic adds: the summation order is not deterministic).
- * dY is m x k (lddy >= k), dX is n x k (lddx >= k), device pointers.
+ * the same streams.  When n x c values of dX (c up to 8) fit in LDS beside
+ * the tables, every CU scatters into its own copy with LDS atomic adds and a
+ * second kernel sums the copies (the copies live in the handle's scratch);
+ * otherwise the scatter uses global atomic adds.  Either way the summation
+ * order is not deterministic.  dY is m x k (lddy >= k), dX is n x k
+ * (lddx >= k), device pointers.
  */
 dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t lddy, void *dX,
                           int64_t lddx, double alpha, double beta, void *stream);

@@ -701,8 +701,14 @@ dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t 
     if (lddy < k || lddx < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
     if (lddx >= (1ll << 31) || lddy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
     if ((c.n > 0 && !dX) || (c.m > 0 && c.nnz > 0 && !dY)) return set_err(DTANS_EINVAL, "null vector");
+    // the per-CU blocks of dX live in the handle's scratch (see launch_spmm_t)
+    const size_t wb = spmm_t_work_bytes(mat->view, c.dtype == kF64, mat->num_cus);
+    if (wb > 0 && c.nnz > 0) {
+        s = ensure_partial(mat->partial, mat->partial_cap, wb / 8 + 1);
+        if (s) return s;
+    }
     hipError_t e = launch_spmm_t(mat->view, c.dtype == kF64, k, dY, lddy, dX, lddx, alpha, beta,
-                                 plan_launch(mat), st);
+                                 plan_launch(mat), mat->partial, 8 * mat->partial_cap, st);
     if (e != hipSuccess) return hip_err(e, "dtans_spmm_t launch");
     return DTANS_OK;
 }

@@ -330,6 +330,48 @@ struct TransSink {
     __device__ __forceinline__ void finish_lane(int32_t, int, bool) {}
 };
 
+// Position of element i of the LDS block of dX: one spare slot after every 32,
+// so that lanes whose columns lie a multiple of 32 / KC apart (equal lane
+// lengths over a regular row walk exactly such strides) do not all hit one
+// LDS bank.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 5); }
+
+// dX (k columns) += A^T dY into a block of dX in LDS (trans_lds_kernel);
+// alpha is applied when the copies are summed
+template <typename VT, int KC>
+struct TransLdsSink {
+    static constexpr int kOcc = 4;
+    struct Params {
+        const VT *dY;
+        uint32_t lddy;
+        VT *lds;  // n x KC, set by the kernel
+    };
+    const Params p;
+    int32_t cur;
+    VT dy[KC];
+    __device__ TransLdsSink(const Params &pp, int64_t, int32_t, bool) : p(pp), cur(-1) {}
+    __device__ __forceinline__ void load_row(int32_t row) {
+        cur = row;
+        const VT *src = p.dY + (uint64_t)(uint32_t)row * p.lddy;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) dy[c] = src[c];
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
+                                            int64_t, const int32_t rowk[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nreal) {
+                if (rowk[k] != cur) load_row(rowk[k]);
+#pragma unroll
+                for (int c = 0; c < KC; ++c) atomicAdd(p.lds + lds_slot(col[k] * KC + c), v[k] * dy[c]);
+            }
+    }
+    __device__ __forceinline__ void pre_step() {}
+    __device__ __forceinline__ void finish_row(int32_t, int) {}
+    __device__ __forceinline__ void finish_lane(int32_t, int, bool) {}
+};
+
 // decode to CSR: column and value bits of every nonzero
 template <typename VT>
 struct DecodeSink {
@@ -811,12 +853,11 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
     }
 }
 
-// MINW: waves per SIMD the register allocation must allow (8 lets two
-// 16-wave workgroups share a CU, which is what the LDS tables permit)
-template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
-__global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
-    __shared__ uint64_t s_tab[kSlots];
-    __shared__ VT s_val[kSlots];
+// The sweep of one persistent workgroup over its encoded waves (tables
+// staged into s_tab / s_val on the way).
+template <int LAYOUT, typename VT, class Sink, int TF>
+__device__ __forceinline__ void decode_sweep(const DevMat &a, const typename Sink::Params &sp,
+                                             uint64_t *s_tab, VT *s_val) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t total = (int64_t)gridDim.x * wpb;
@@ -844,6 +885,58 @@ __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename S
     } else {
         decode_rows<VT, Sink, TF>(a, s_tab, s_val, lane, sp, s_end, s0, stride, share);
     }
+}
+
+// MINW: waves per SIMD the register allocation must allow (8 lets two
+// 16-wave workgroups share a CU, which is what the LDS tables permit)
+template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
+__global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
+    __shared__ uint64_t s_tab[kSlots];
+    __shared__ VT s_val[kSlots];
+    decode_sweep<LAYOUT, VT, Sink, TF>(a, sp, s_tab, s_val);
+}
+
+// Transposed product with dX privatised in LDS: a workgroup (one per CU)
+// scatters into its own copy of the n x KC block of dX with LDS atomic adds,
+// then writes it to part[blockIdx.x]; trans_reduce_kernel sums the copies.
+// No global atomics, so no contention when n is small (the tall pruned
+// weight: every column of dX receives thousands of contributions).
+template <int LAYOUT, typename VT, int KC, int TF>
+__global__ __launch_bounds__(1024, 4) void trans_lds_kernel(DevMat a,
+                                                            typename TransLdsSink<VT, KC>::Params sp,
+                                                            VT *part) {
+    __shared__ uint64_t s_tab[kSlots];
+    __shared__ VT s_val[kSlots];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    VT *s_dx = (VT *)s_dyn;
+    const int64_t cnt = a.n * KC, slots = lds_slot((uint32_t)cnt);
+    for (int64_t i = threadIdx.x; i < slots; i += blockDim.x) s_dx[i] = (VT)0;
+    // (the table staging inside the sweep ends with a barrier, which also
+    // orders these stores before the first scatter)
+    typename TransLdsSink<VT, KC>::Params q = sp;
+    q.lds = s_dx;
+    decode_sweep<LAYOUT, VT, TransLdsSink<VT, KC>, TF>(a, q, s_tab, s_val);
+    __syncthreads();
+    VT *dst = part + (int64_t)blockIdx.x * cnt;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) dst[i] = s_dx[lds_slot((uint32_t)i)];
+}
+
+// dX (KC columns) = alpha * (sum of the G copies) + beta * dX
+template <typename VT>
+__global__ __launch_bounds__(256) void trans_reduce_kernel(const VT *part, int64_t G, int64_t n,
+                                                           int KC, VT *dX, int64_t lddx,
+                                                           double alpha, double beta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cnt = n * KC;
+    if (i >= cnt) return;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eight loads in flight
+    int64_t b = 0;
+    for (; b + 8 <= G; b += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += (double)part[(b + u) * cnt + i];
+    for (; b < G; ++b) acc[0] += (double)part[b * cnt + i];
+    const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    VT *d = dX + (i / KC) * lddx + i % KC;
+    *d = (VT)(beta == 0.0 ? alpha * sum : alpha * sum + beta * (double)*d);
 }
 
 // Same work as decode_kernel, with every wavefront owning one contiguous run
@@ -1401,10 +1494,52 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
     });
 }
 
+// Columns of dX per pass of the LDS-privatised transpose (0: dX does not fit,
+// use global atomics): the widest of 8, 4, 2, 1 whose n x KC block fits in
+// LDS beside the tables, one 1024-thread workgroup per CU.
+template <typename VT>
+int trans_lds_cols(const DevMat &a) {
+    const int64_t room = 160 * 1024 - 1024 - (int64_t)kSlots * (8 + (int64_t)sizeof(VT));
+    for (int c : {8, 4, 2, 1})
+        if ((a.n * c + a.n * c / 32 + 1) * (int64_t)sizeof(VT) <= room && a.n * c < (1ll << 31)) return c;
+    return 0;
+}
+
 template <typename VT>
 hipError_t spmm_t_impl(const DevMat &a, int k, const VT *dY, int64_t lddy, VT *dX, int64_t lddx,
-                       double alpha, double beta, Launch L, hipStream_t st) {
+                       double alpha, double beta, Launch L, void *work, size_t work_bytes,
+                       hipStream_t st) {
     if (a.n == 0) return hipSuccess;
+    const int kcl = trans_lds_cols<VT>(a);
+    const int64_t G = L.num_cus;
+    if (kcl > 0 && a.nnz > 0 && a.num_waves > 0 &&
+        work_bytes >= (size_t)G * (size_t)a.n * (size_t)kcl * sizeof(VT)) {
+        VT *part = (VT *)work;
+        return for_kc(k, kcl, [&](auto KCc, int c0) {
+            constexpr int KC = decltype(KCc)::value;
+            if constexpr (KC > 8) {
+                return hipErrorInvalidValue;  // excluded by kcl
+            } else {
+                typename TransLdsSink<VT, KC>::Params sp;
+                sp.dY = dY + c0;
+                sp.lddy = (uint32_t)lddy;
+                sp.lds = nullptr;
+                const size_t dyn = ((size_t)a.n * KC + (size_t)a.n * KC / 32 + 1) * sizeof(VT);
+                auto kern = a.layout == 1 ? pick_bd(a, trans_lds_kernel<1, VT, KC, 1>, trans_lds_kernel<1, VT, KC, 0>)
+                                          : pick_bd(a, trans_lds_kernel<2, VT, KC, 1>, trans_lds_kernel<2, VT, KC, 0>);
+                hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(1024), dyn, st, a, sp, part);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                const int64_t cnt = a.n * KC;
+                hipLaunchKernelGGL(trans_reduce_kernel<VT>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                                   st, (const VT *)part, G, a.n, KC, dX + c0, lddx, alpha, beta);
+                return hipGetLastError();
+            }
+        });
+    }
     return for_kc(k, [&](auto KCc, int c0) {
         constexpr int KC = decltype(KCc)::value;
         const int64_t tot = a.n * KC;
@@ -1511,13 +1646,19 @@ hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t 
                             st);
 }
 
+size_t spmm_t_work_bytes(const DevMat &a, bool f64, int num_cus) {
+    const int c = f64 ? trans_lds_cols<double>(a) : trans_lds_cols<float>(a);
+    return (size_t)num_cus * (size_t)a.n * (size_t)c * (f64 ? 8 : 4);
+}
+
 hipError_t launch_spmm_t(const DevMat &a, bool f64, int k, const void *dY, int64_t lddy, void *dX,
-                         int64_t lddx, double alpha, double beta, Launch L, hipStream_t st) {
+                         int64_t lddx, double alpha, double beta, Launch L, void *work,
+                         size_t work_bytes, hipStream_t st) {
     if (f64)
         return spmm_t_impl<double>(a, k, (const double *)dY, lddy, (double *)dX, lddx, alpha, beta,
-                                   L, st);
+                                   L, work, work_bytes, st);
     return spmm_t_impl<float>(a, k, (const float *)dY, lddy, (float *)dX, lddx, alpha, beta, L,
-                              st);
+                              work, work_bytes, st);
 }
 
 hipError_t launch_decode(const DevMat &a, bool f64, int32_t *col, void *vals, Launch L,

@@ -51,9 +51,14 @@ struct Launch {
 hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, double alpha, double beta, double *partial, Launch L,
                        hipStream_t st);
-// dX = alpha*A^T*dY + beta*dX via decode-and-scatter
+// dX = alpha*A^T*dY + beta*dX via decode-and-scatter.  When an n x c block
+// of dX fits in LDS (c >= 1) and `work` holds spmm_t_work_bytes, each CU
+// scatters into its own block and the blocks are summed; otherwise global
+// atomic adds.
+size_t spmm_t_work_bytes(const DevMat &a, bool f64, int num_cus);
 hipError_t launch_spmm_t(const DevMat &a, bool f64, int k, const void *dY, int64_t lddy, void *dX,
-                         int64_t lddx, double alpha, double beta, Launch L, hipStream_t st);
+                         int64_t lddx, double alpha, double beta, Launch L, void *work,
+                         size_t work_bytes, hipStream_t st);
 // decode to CSR (col / raw value bits); row_ptr copied by the caller
 hipError_t launch_decode(const DevMat &a, bool f64, int32_t *col, void *vals, Launch L,
                          hipStream_t st);
