@@ -14,6 +14,12 @@ multiplication on a single copy, back to back ("warm"), and the plain HIP CSR
 kernel on the same GPU are reported alongside, as is the CPU oracle on the
 host cores.
 
+Other workloads (--workload): band (4096 x 4096, FP64 SpMV), rmat (scale 22,
+FP32 SpMV), pruned1 / pruned8 / pruned32 (11008 x 4096 BF16-valued FP32
+weight, SpMV / SpMM with k = 8 / 32), batch (64 banded FP32 matrices in one
+persistent launch, against one CSR launch per matrix) and autograd (forward
+SpMM and backward transposed product with batch 16 on the pruned weight).
+
 Prints one JSON line (see the keys below).
 """
 from __future__ import annotations
@@ -137,7 +143,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="stencil")
+    ap.add_argument("--workload", default="stencil",
+                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch or autograd")
     ap.add_argument("--layout", default="auto")
     ap.add_argument("--lane-nnz", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
