@@ -375,3 +375,39 @@ def test_long_split_rows(T, dtype):
         for c in range(k):
             scale = oracle.absmv(rp, ci, v, X[:, c])
             assert rel_error(Y[:, c], Yref[:, c], scale) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("layout,T", [("row", 0), ("nnz", 32)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_spmm_t_both_paths(layout, T, dtype):
+    """The transposed product with dX privatised in LDS (n small enough for one
+    column of dX beside the tables) and with global atomics (n just too large)
+    agree with the oracle; k = 5 spans several LDS passes."""
+    torch = need_gpu()
+    vb = np.dtype(dtype).itemsize
+    room = 160 * 1024 - 1024 - 4096 * (8 + vb)
+    n_fit = (room // vb - 1) * 32 // 33  # largest n whose one-column block fits
+    for n in (n_fit, n_fit + 64):
+        rng = np.random.default_rng(n)
+        m = 1500
+        lens = rng.integers(0, 40, size=m)
+        rp = np.zeros(m + 1, np.int64)
+        rp[1:] = np.cumsum(lens)
+        ci = np.concatenate([np.sort(rng.choice(n, size=L, replace=False)) for L in lens]).astype(np.int32)
+        v = rng.choice([0.5, -1.5, 2.0, 0.25], size=len(ci)).astype(dtype)
+        rp = rp.astype(np.int32)
+        progress("spmm_t paths n=%d %s %s" % (n, layout, dtype.__name__))
+        A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, lane_nnz=T)
+        k = 5
+        dY = workloads.vector(m, 6, dtype, k=k)
+        dX0 = workloads.vector(n, 3, dtype, k=k)
+        dX = torch.from_numpy(dX0.copy()).cuda()
+        A.spmm_t(torch.from_numpy(dY).cuda(), dX, alpha=-0.75, beta=0.5)
+        out = dX.cpu().numpy()
+        At = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
+        At.sort_indices()
+        for c in range(k):
+            ref = oracle.spmtv(rp, ci, v, n, dY[:, c], dX0[:, c], alpha=-0.75, beta=0.5)
+            scale = 0.75 * oracle.absmv(At.indptr, At.indices, At.data, dY[:, c]) + \
+                0.5 * np.abs(dX0[:, c].astype(np.float64))
+            assert rel_error(out[:, c], ref, scale) <= TOL[dtype], (n, c)
