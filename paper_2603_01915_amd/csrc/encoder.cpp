@@ -561,7 +561,9 @@ void put_table(std::vector<uint8_t> &b, size_t off, const Table &t) {
     }
 }
 
-std::string get_table(const uint8_t *b, Table &t, bool is_delta) {
+// sym_bits: width of a table symbol (delta keys below 2^30 are checked
+// separately; FP32 values are 32-bit patterns)
+std::string get_table(const uint8_t *b, Table &t, bool is_delta, int sym_bits = 64) {
     t = Table();
     int counts[kSlots + 1];
     (void)counts;
@@ -579,7 +581,8 @@ std::string get_table(const uint8_t *b, Table &t, bool is_delta) {
             t.has_escape = true;
         } else if (is_delta && t.sym[i] >= kDeltaLimit) {
             return fail("ECORRUPT", "table delta above 2^30");
-        } else if (!is_delta && t.sym[i] >> 32 && false) {
+        } else if (sym_bits < 64 && (t.sym[i] >> sym_bits) != 0) {
+            return fail("ECORRUPT", "table value wider than the value type");
         }
     }
     // every symbol must own exactly `base` slots with digits 0..base-1
@@ -694,7 +697,7 @@ std::string load_container(const std::string &path, Container &c) {
     const size_t o_ev = sz; sz = al8(sz + vb * (size_t)nv);
     if (sz != b.size()) return fail("ECORRUPT", "file size does not match the header");
     std::string e = get_table(&b[o_dt], c.dtab, true);
-    if (e.empty()) e = get_table(&b[o_vt], c.vtab, false);
+    if (e.empty()) e = get_table(&b[o_vt], c.vtab, false, c.dtype == kF32 ? 32 : 64);
     if (!e.empty()) return e;
     c.row_ptr.resize(c.m + 1);
     memcpy(c.row_ptr.data(), &b[o_rp], 4 * (size_t)(c.m + 1));

@@ -159,6 +159,25 @@ def test_corrupted_container_rejected(tmp_path):
     assert e.value.status == _lib.ECORRUPT
 
 
+def test_wide_fp32_value_symbol_rejected(tmp_path):
+    """An FP32 container whose value table holds a symbol wider than 32 bits
+    (consistent checksum, written by the oracle's container writer) is
+    refused on load."""
+    rp = np.array([0, 2, 3], np.int32)
+    ci = np.array([0, 1, 1], np.int32)
+    v = np.array([1.5, 2.5, -1.0], np.float32)
+    path = str(tmp_path / "w.dtans")
+    P.Matrix.from_csr(rp, ci, v, 2).save(path)
+    c = container.read(path)
+    i = next(j for j, s in enumerate(c.vtab.symbol) if s is not None and s != container.ESC)
+    old = c.vtab.symbol[i]
+    c.vtab.symbol = [(s | (1 << 40)) if s == old else s for s in c.vtab.symbol]
+    container.write(path, c)
+    with pytest.raises(P.DtansError) as e:
+        P.Matrix.load(path)
+    assert e.value.status == _lib.ECORRUPT
+
+
 def test_info_statistics():
     rp, ci, v = workloads.stencil27(16)
     A = P.Matrix.from_csr(rp, ci, v, 16 ** 3, layout="row")
