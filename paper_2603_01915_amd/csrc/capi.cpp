@@ -336,20 +336,21 @@ void auto_encoding(int64_t m, int64_t nnz, const int32_t *row_ptr, const dtans_e
     if (layout == DTANS_LAYOUT_NNZ) {
         T = o.lane_nnz;
         if (T == 0) {
+            // wavefronts the SpMV launch keeps resident on 256 CUs
+            int wpw = 0, wgcu = 0;
+            default_shape(f64, 7, wpw, wgcu);
+            const int64_t resident = 256LL * wpw * wgcu;
             int64_t t;
             if (maxlen <= 4 * std::max(mean, 1.0)) {
                 // regular rows: encoded waves cost about the same, so give
-                // every wavefront the SpMV launch keeps resident exactly one
-                // of them: a second, partial round would double the time of
-                // a share
-                int wpw = 0, wgcu = 0;
-                default_shape(f64, 7, wpw, wgcu);
-                const int64_t resident = 256LL * wpw * wgcu;
+                // every resident wavefront exactly one of them: a second,
+                // partial round would double the time of a share
                 t = (nnz + 64 * resident - 1) / (64 * resident);
             } else {
-                // irregular rows: the cost of a wave varies with its rows,
-                // several per wavefront even it out
-                t = nnz / (256LL * 4 * 8 * 64);
+                // irregular rows: the cost of a wave varies with its rows;
+                // about four per wavefront even it out (R-MAT scale 22:
+                // 0.574 ms at 4.3 waves per wavefront, 0.617 at 1.3)
+                t = nnz / (64 * resident * 4);
             }
             T = (int)std::min<int64_t>(512, std::max<int64_t>(32, (t + 3) / 4 * 4));
         }
