@@ -1,6 +1,6 @@
-"""Autograd: forward A X and backward A^T dY (decode-and-scatter) checked with
-torch.autograd.gradcheck in FP64, central differences in FP64 on the pruned
-weight, and the oracle's A^T dy."""
+"""Autograd: forward A X and backward A^T dY (decode-and-scatter, or a product
+on an encoded transpose) checked with torch.autograd.gradcheck in FP64,
+central differences in FP64 on the pruned weight, and the oracle's A^T dy."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -16,7 +16,7 @@ P = pytest.importorskip("paper_2603_01915_amd")
 
 def test_gradcheck_small():
     torch = need_gpu()
-    from paper_2603_01915_amd.autograd import DtansLinearFn
+    from paper_2603_01915_amd.autograd import DtansLinearFn, transpose_csr
 
     rng = np.random.default_rng(12)
     m, n = 96, 80
@@ -35,31 +35,41 @@ def test_gradcheck_small():
         x = torch.randn(n, dtype=torch.float64, device="cuda", requires_grad=True)
         assert torch.autograd.gradcheck(lambda x: DtansLinearFn.apply(A, x), (x,), eps=1e-6,
                                         atol=1e-9, rtol=1e-7, nondet_tol=1e-12)
+        # with an encoded transpose the backward has one writer per entry
+        rpt, cit, vt = transpose_csr(rp, ci, v, n)
+        At = P.Matrix.from_csr(rpt, cit, vt, m, layout=layout, lane_nnz=T)
+        assert torch.autograd.gradcheck(lambda X: DtansLinearFn.apply(A, X, At), (X,), eps=1e-6,
+                                        atol=1e-9, rtol=1e-7)
+        assert torch.autograd.gradcheck(lambda x: DtansLinearFn.apply(A, x, At), (x,), eps=1e-6,
+                                        atol=1e-9, rtol=1e-7)
 
 
-def test_pruned_forward_backward_against_oracle():
-    """Config 5: the pruned 11008 x 4096 BF16-valued weight, batch 16 FP32."""
+@pytest.mark.parametrize("transposed_copy", [False, True])
+def test_pruned_forward_backward_against_oracle(transposed_copy):
+    """The pruned 11008 x 4096 BF16-valued weight, batch 16 FP32; the backward
+    by decode-and-scatter or on an encoded transpose."""
     torch = need_gpu()
-    from paper_2603_01915_amd.autograd import DtansLinearFn
+    from paper_2603_01915_amd.autograd import DtansLinearFn, transpose_csr
 
     rp, ci, v = workloads.pruned_weight()
     m, n = 11008, 4096
     A = P.Matrix.from_csr(rp, ci, v, n)
+    At = P.Matrix.from_csr(*transpose_csr(rp, ci, v, n), m) if transposed_copy else None
     X = torch.from_numpy(workloads.vector(n, 5, np.float32, k=16)).cuda().requires_grad_(True)
     dY = workloads.vector(m, 6, np.float32, k=16)
-    progress("pruned forward/backward")
-    Y = DtansLinearFn.apply(A, X)
+    progress("pruned forward/backward, transposed copy %s" % transposed_copy)
+    Y = DtansLinearFn.apply(A, X, At)
     Y.backward(torch.from_numpy(dY).cuda())
     Yh = Y.detach().cpu().numpy()
     dX = X.grad.cpu().numpy()
     Xh = X.detach().cpu().numpy()
-    At = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
-    At.sort_indices()
+    St = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
+    St.sort_indices()
     for c in range(0, 16, 3):
         y_ref = oracle.spmv(rp, ci, v, Xh[:, c])
         assert rel_error(Yh[:, c], y_ref, oracle.absmv(rp, ci, v, Xh[:, c])) <= TOL[np.float32]
         g_ref = oracle.spmtv(rp, ci, v, n, dY[:, c])
-        scale = oracle.absmv(At.indptr, At.indices, At.data, dY[:, c])
+        scale = oracle.absmv(St.indptr, St.indices, St.data, dY[:, c])
         assert rel_error(dX[:, c], g_ref, scale) <= TOL[np.float32]
 
 
@@ -98,13 +108,14 @@ def test_pruned_central_differences_fp64():
             assert abs(fd - g) <= 1e-6 * (1 + abs(g)), (j, b, fd, g)
 
 
-def test_linear_module():
+@pytest.mark.parametrize("transposed_copy", [False, True])
+def test_linear_module(transposed_copy):
     torch = need_gpu()
     from paper_2603_01915_amd.autograd import DtansLinear
 
     rp, ci, v = workloads.pruned_weight(rows=200, cols=128)
-    A = P.Matrix.from_csr(rp, ci, v, 128)
-    lin = DtansLinear(A)
+    lin = DtansLinear.from_csr(rp, ci, v, 128, transposed_copy=transposed_copy)
+    assert (lin.At is not None) == transposed_copy
     x = torch.randn(5, 128, device="cuda", requires_grad=True)
     y = lin(x)
     assert tuple(y.shape) == (5, 200)

@@ -380,3 +380,20 @@ def test_autotune_without_gpu_fails_loudly():
     with pytest.raises(P.DtansError) as e:
         P.autotune(rp, ci, v, 64, budget_s=1.0)
     assert e.value.status == _lib.EHIP
+
+
+def test_transpose_csr_matches_scipy():
+    """The host transpose used for an encoded A^T (autograd backward) equals
+    scipy's, including empty rows and columns and a ragged tail."""
+    from paper_2603_01915_amd.autograd import transpose_csr
+
+    for m, n, dens, seed in ((37, 53, 0.08, 1), (1, 9, 0.5, 2), (64, 3, 0.4, 3), (5, 5, 0.0, 4)):
+        rp, ci, v = rand_csr(m, n, dens, seed)
+        rpt, cit, vt = transpose_csr(rp, ci, v, n)
+        T = sp.csr_matrix((v, ci, rp), shape=(m, n)).T.tocsr()
+        T.sort_indices()
+        assert rpt.dtype == np.int32 and cit.dtype == np.int32 and vt.dtype == v.dtype
+        assert np.array_equal(rpt, T.indptr) and np.array_equal(cit, T.indices)
+        assert np.array_equal(vt, T.data)
+    with pytest.raises(ValueError):
+        transpose_csr(np.array([0, 1], np.int32), np.array([4], np.int32), np.ones(1), 4)
