@@ -17,8 +17,11 @@ host cores.
 Other workloads (--workload): band (4096 x 4096, FP64 SpMV), rmat (scale 22,
 FP32 SpMV), pruned1 / pruned8 / pruned32 (11008 x 4096 BF16-valued FP32
 weight, SpMV / SpMM with k = 8 / 32), batch (64 banded FP32 matrices in one
-persistent launch, against one CSR launch per matrix) and autograd (forward
-SpMM and backward transposed product with batch 16 on the pruned weight).
+persistent launch, against one CSR launch per matrix), autograd (forward
+SpMM and backward transposed product with batch 16 on the pruned weight) and
+encode (host arrays to container: the host encoder against the one whose
+stream base/digit passes and word interleave run on the GPU, on the stencil
+and the pruned weight).
 
 Prints one JSON line (see the keys below).
 """
@@ -144,7 +147,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="stencil",
-                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch or autograd")
+                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch, autograd or encode")
     ap.add_argument("--layout", default="auto")
     ap.add_argument("--lane-nnz", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
@@ -185,6 +188,8 @@ def main():
         return bench_batch(args, torch, P)
     if args.workload == "autograd":
         return bench_autograd(args, torch, P)
+    if args.workload == "encode":
+        return bench_encode(args, torch, P)
     log("generating workload %s" % args.workload)
     W = make_workload(args.workload)
     rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
@@ -399,6 +404,50 @@ def bench_autograd(args, torch, P):
         res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),
                                "copies_rotated": ccopies}
         res["speedup_vs_csr"] = round(cms / ms, 3)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_encode(args, torch, P):
+    """Encoding throughput (nonzeros per second, host CSR arrays in, host
+    container out) of dtans_encode_csr and dtans_encode_csr_gpu, whose
+    containers are identical; each is the best of `steps` (at most 5) calls.
+    The GPU call includes its uploads, the word pass and the download."""
+    import workloads
+
+    steps = max(1, min(args.steps, 5))
+    cases = []
+    rp, ci, v = workloads.stencil27(128)
+    cases.append(("stencil27 128^3 fp64, row layout", rp, ci, v, 128 ** 3, "row"))
+    rp, ci, v = workloads.pruned_weight()
+    cases.append(("pruned 11008x4096 fp32, nnz layout", rp, ci, v, 4096, "auto"))
+    out = []
+    for name, rp, ci, v, n, layout in cases:
+        times = {}
+        for gpu in (False, True):
+            best = None
+            for _ in range(steps + (1 if gpu else 0)):  # one untimed GPU call first
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, gpu_encode=gpu)
+                dt = time.perf_counter() - t0
+                A.close()
+                best = dt if best is None else min(best, dt)
+            times[gpu] = best
+            log("%s: %s encoder %.3f s" % (name, "GPU" if gpu else "host", best))
+        out.append({"workload": name, "nnz": len(ci), "host_s": round(times[False], 4),
+                    "gpu_s": round(times[True], 4),
+                    "host_Mnnz_per_s": round(len(ci) / times[False] / 1e6, 1),
+                    "gpu_Mnnz_per_s": round(len(ci) / times[True] / 1e6, 1),
+                    "speedup": round(times[False] / times[True], 3)})
+    res = {"metric": "encode throughput (host CSR arrays to container)", "value": out[0]["gpu_Mnnz_per_s"],
+           "unit": "Mnnz/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+           "ms_per_step": round(out[0]["gpu_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
+           "config": {"workload": "encode " + out[0]["workload"]}, "cases": out,
+           "host_threads": min(os.cpu_count() or 4, 32), "roofline": None,
+           "note": "word-pass kernel times are in the rocprofv3 kernel trace; the rest of either call "
+                   "(keys, alphabet fit, tables, symbol lookup, escapes) runs on the host"}
     print(json.dumps(res), flush=True)
     return 0
 

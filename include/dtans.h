@@ -127,6 +127,22 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
                               const int32_t *col_idx, const void *vals, dtans_dtype dtype,
                               const dtans_encode_opts *opts, dtans_matrix **out);
 
+/*
+ * Same arguments, result and errors as dtans_encode_csr, and a container
+ * byte-identical to its: the per-stream base and digit passes (Sec. IV-E) and
+ * the interleave of each wave's streams in the decoder's load order
+ * (Sec. IV-B) run on the current GPU, on `stream` (a hipStream_t, NULL = the
+ * null stream); the alphabet fit, tables and escape regions stay on the host.
+ * All arrays are host pointers; the call allocates its own device buffers
+ * (about 8 bytes per nonzero plus the words), frees them before returning and
+ * blocks until the words are back on the host.  DTANS_EHIP / DTANS_ENOMEM for
+ * runtime or allocation failures; DTANS_ECORRUPT if the device's word counts
+ * disagree (never expected).
+ */
+dtans_status dtans_encode_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                  const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                                  const dtans_encode_opts *opts, void *stream, dtans_matrix **out);
+
 /* Write / read the container file (Sec. II-A: the encoded matrix can be kept
  * for repeated decoding).  dtans_load checks the checksum and structure and
  * verifies by a full host decode before returning a handle. */

@@ -99,7 +99,11 @@ class Matrix:
     def from_csr(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
                  waves_per_wg: int = 0, wg_per_cu: int = 0, sort_rows: bool = False,
                  seed: int = 1, stream_stage: int = 0, max_mult: int = 0,
-                 first_delta_column: bool = False) -> "Matrix":
+                 first_delta_column: bool = False, gpu_encode: bool = False,
+                 stream=None) -> "Matrix":
+        """Encode host CSR arrays.  ``gpu_encode`` runs the streams' base and
+        digit passes and the word interleave on the current GPU (the same
+        container as the host encoder's)."""
         L = _lib.load()
         rp = _np(row_ptr, np.int32)
         ci = _np(col, np.int32)
@@ -119,8 +123,12 @@ class Matrix:
         o.max_mult = max_mult
         o.first_delta_column = int(bool(first_delta_column))
         h = ctypes.c_void_p()
-        _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
-                                      ctypes.byref(o), ctypes.byref(h)))
+        if gpu_encode:
+            _lib.check(L.dtans_encode_csr_gpu(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
+                                              ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        else:
+            _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
+                                          ctypes.byref(o), ctypes.byref(h)))
         return cls(h.value)
 
     @classmethod

@@ -29,7 +29,7 @@ dtans_status from_msg(const std::string &m) {
     struct { const char *p; dtans_status s; } map[] = {
         {"EINVAL", DTANS_EINVAL}, {"EUNSORTED", DTANS_EUNSORTED}, {"ERANGE", DTANS_ERANGE},
         {"ENOMEM", DTANS_ENOMEM}, {"ECORRUPT", DTANS_ECORRUPT}, {"EIO", DTANS_EIO},
-        {"EUNSUPPORTED", DTANS_EUNSUPPORTED}};
+        {"EUNSUPPORTED", DTANS_EUNSUPPORTED}, {"EHIP", DTANS_EHIP}};
     for (auto &e : map)
         if (m.compare(0, strlen(e.p), e.p) == 0 && m.size() > strlen(e.p) && m[strlen(e.p)] == ':')
             return set_err(e.s, m);
@@ -515,9 +515,12 @@ void dtans_default_opts(dtans_encode_opts *o) {
     o->perm_seed = 1;
 }
 
-dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
-                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
-                              const dtans_encode_opts *opts, dtans_matrix **out) {
+namespace {
+
+dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                           const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                           const dtans_encode_opts *opts, WordCoder coder, void *coder_ctx,
+                           dtans_matrix **out) {
     if (!out) return set_err(DTANS_EINVAL, "out is null");
     *out = nullptr;
     dtans_encode_opts o;
@@ -565,7 +568,7 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
     if (p.layout == kLayoutNnz) p.lane_nnz = (uint32_t)T;
     dtans_matrix *h = new dtans_matrix();
-    std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c);
+    std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c, coder, coder_ctx);
     if (!err.empty()) {
         delete h;
         return from_msg(err);
@@ -575,6 +578,20 @@ dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *
     h->stage = o.stream_stage;
     *out = h;
     return DTANS_OK;
+}
+
+}  // namespace
+
+dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                              const dtans_encode_opts *opts, dtans_matrix **out) {
+    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, nullptr, nullptr, out);
+}
+
+dtans_status dtans_encode_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                  const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                                  const dtans_encode_opts *opts, void *stream, dtans_matrix **out) {
+    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, device_word_coder, stream, out);
 }
 
 dtans_status dtans_save(const dtans_matrix *mat, const char *path) {

@@ -385,7 +385,7 @@ struct WaveOut {
 // ---------------------------------------------------------------- encode
 std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col, const void *vals, uint32_t dtype,
-                       const EncodeParams &p, Container &c) {
+                       const EncodeParams &p, Container &c, WordCoder coder, void *coder_ctx) {
     if (m < 0 || n < 0 || nnz < 0) return fail("EINVAL", "negative size");
     if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31))
         return fail("ERANGE", "rows, columns and nonzeros must be below 2^31");
@@ -484,6 +484,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
                 cnts[q] = 0;
                 if (l < c.num_lanes) c.lane_range(l, g0s[q], cnts[q]);
                 int64_t S = (cnts[q] + 3) / 4;
+                maxS = std::max(maxS, S);
+                if (coder) continue;
                 sym.resize(8 * S);
                 for (int64_t t = 0; t < 4 * S; ++t) {
                     if (t < cnts[q]) {
@@ -496,12 +498,11 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
                 }
                 lanes[q] = LaneCode();
                 encode_lane(sym.data(), S, dsm, vsm, lanes[q]);
-                maxS = std::max(maxS, S);
             }
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3 && !coder; ++k)
                 for (int q = 0; q < kWave; ++q)
                     if (lanes[q].S > 0) o.words.push_back(lanes[q].init[k]);
-            for (int64_t j = 0; j + 1 < maxS; ++j) {
+            for (int64_t j = 0; j + 1 < maxS && !coder; ++j) {
                 for (int q = 0; q < kWave; ++q)
                     if (j < lanes[q].S - 1 && lanes[q].load[2 * j]) o.words.push_back(lanes[q].w[3 * j]);
                 for (int q = 0; q < kWave; ++q)
@@ -542,6 +543,26 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     c.word_off.push_back(c.words.size());
     c.escd_off.push_back(c.escd.size());
     c.escv_off.push_back(c.escv.size());
+    if (coder) {
+        WordJob job;
+        job.c = &c;
+        job.dsym = dsym.data();
+        job.vsym = vsym.data();
+        job.dpad = dpad;
+        job.vpad = vpad;
+        auto meta = [](const SlotMap &sm, std::vector<uint32_t> &mt, std::vector<uint16_t> &sl) {
+            mt.resize(sm.mult.size());
+            for (size_t s = 0; s < sm.mult.size(); ++s)
+                mt[s] = (uint32_t)sm.first[s] | ((uint32_t)sm.mult[s] << 16);
+            sl = sm.slots;
+        };
+        meta(dsm, job.dmeta, job.dslots);
+        meta(vsm, job.vmeta, job.vslots);
+        std::string err = coder(job, coder_ctx, c.words, c.word_off);
+        if (!err.empty()) return err;
+        if (c.word_off.size() != (size_t)c.num_waves + 1 || c.word_off.back() != c.words.size())
+            return fail("ECORRUPT", "device word coder returned inconsistent offsets");
+    }
     return "";
 }
 

@@ -1,0 +1,121 @@
+"""The encoder's word pass on the GPU (dtans_encode_csr_gpu): every container
+is byte-identical to the host encoder's and decoded exactly by the oracle,
+over both layouts and value types, rows that are empty, duplicated, very
+long (many 16-step flag words) or escape-heavy, ragged last lanes and waves,
+degenerate sizes, the all-256-bases case where every check extracts, and the
+full-size stencil and pruned weight."""
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from gpu_common import need_gpu, progress
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_01915_amd")
+
+LAYOUTS = [("row", 0), ("nnz", 4), ("nnz", 32), ("nnz", 100)]
+
+
+def rand_csr(m, n, dens, seed, dtype=np.float64, pool=None):
+    rng = np.random.default_rng(seed)
+    A = sp.random(m, n, density=dens, format="csr", random_state=rng)
+    A.sort_indices()
+    v = rng.standard_normal(A.nnz) if pool is None else rng.choice(rng.standard_normal(pool), A.nnz)
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), v.astype(dtype)
+
+
+def both(tmp_path, tag, rp, ci, v, n, **kw):
+    """Encode on the host and with the GPU word pass; the two files must be
+    equal byte for byte, and the oracle must decode the GPU's exactly."""
+    need_gpu()
+    progress("encoder %s" % tag)
+    A = P.Matrix.from_csr(rp, ci, v, n, **kw)
+    B = P.Matrix.from_csr(rp, ci, v, n, gpu_encode=True, **kw)
+    pa, pb = str(tmp_path / (tag + "_host.dtans")), str(tmp_path / (tag + "_gpu.dtans"))
+    A.save(pa)
+    B.save(pb)
+    assert open(pa, "rb").read() == open(pb, "rb").read(), tag
+    r2, c2, v2 = oracle.decode(pb)
+    assert np.array_equal(r2, rp) and np.array_equal(c2, ci)
+    assert np.array_equal(np.asarray(v2).view(np.uint8), np.asarray(v).view(np.uint8))
+    return B
+
+
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_random_matrices(tmp_path, layout, T, dtype):
+    rp, ci, v = rand_csr(700, 500, 0.02, 1, dtype, pool=300)
+    both(tmp_path, "rand_%s_%d" % (layout, T), rp, ci, v, 500, layout=layout, lane_nnz=T)
+
+
+def test_adversarial_rows(tmp_path):
+    rng = np.random.default_rng(3)
+    n = 2 ** 31 - 1
+    rows = [[], [7], [1, 2], [0, 0, 3], [], [2 ** 30, 2 ** 31 - 2], [4999], [], [5, 5, 5, 5, 5],
+            list(range(100, 113)), list(range(0, 20000, 3))]
+    rows += [sorted(rng.choice(10 ** 6, size=rng.integers(0, 9), replace=False)) for _ in range(300)]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], np.int64).astype(np.int32)
+    v = rng.standard_normal(len(ci))
+    v[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, 5e-324]
+    for layout, T in LAYOUTS:
+        both(tmp_path, "adv_%s_%d" % (layout, T), rp.astype(np.int32), ci, v, n, layout=layout, lane_nnz=T)
+
+
+def test_long_rows_many_flag_words(tmp_path):
+    """Rows of 1..1500 nonzeros side by side in one wave: lanes start their
+    backward pass at very different steps and use up to 24 flag words."""
+    rng = np.random.default_rng(9)
+    m, n = 200, 50000
+    lens = rng.integers(1, 1500, size=m)
+    lens[::17] = 0
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(rng.choice(n, size=k, replace=False)) for k in lens]).astype(np.int32)
+    v = rng.choice(rng.standard_normal(40), size=len(ci)).astype(np.float32)
+    both(tmp_path, "long_rows", rp.astype(np.int32), ci, v, n, layout="row")
+    both(tmp_path, "long_rows_nnz", rp.astype(np.int32), ci, v, n, layout="nnz", lane_nnz=512)
+
+
+def test_degenerate_sizes(tmp_path):
+    for m, n in ((0, 5), (5, 5), (1, 1)):
+        rp = np.zeros(m + 1, np.int32)
+        B = both(tmp_path, "empty_%d" % m, rp, np.zeros(0, np.int32), np.zeros(0), n)
+        assert B.info()["words"] == 0
+    # one nonzero; one full wave plus one lane
+    both(tmp_path, "one", np.array([0, 1], np.int32), np.array([0], np.int32), np.ones(1), 1)
+    rp, ci, v = rand_csr(65, 65, 0.3, 4)
+    both(tmp_path, "wave_plus_one", rp, ci, v, 65, layout="row")
+
+
+def test_all_bases_256(tmp_path):
+    """One delta and one value symbol of multiplicity 256: every check
+    extracts, no group loads a word (S + 2 words per lane, Sec. IV-D)."""
+    S, m = 9, 64
+    rp = np.arange(0, m * 4 * S + 1, 4 * S, dtype=np.int32)
+    ci = np.tile(np.arange(1, 4 * S + 1, dtype=np.int32), m)
+    B = both(tmp_path, "bases256", rp, ci, np.ones(len(ci)), 4 * S + 1, layout="row", max_mult=256,
+             first_delta_column=True)
+    assert B.info()["words"] == m * (S + 2)
+
+
+def test_full_size_stencil_and_pruned(tmp_path):
+    torch = need_gpu()
+    rp, ci, v = workloads.stencil27(128)
+    n = 128 ** 3
+    t0 = time.perf_counter()
+    P.Matrix.from_csr(rp, ci, v, n, layout="row")
+    th = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    both(tmp_path, "stencil128", rp, ci, v, n, layout="row")
+    progress("stencil 128^3: host encode %.2f s; host + GPU encodes and checks %.2f s"
+             % (th, time.perf_counter() - t0))
+    rp, ci, v = workloads.pruned_weight()
+    both(tmp_path, "pruned", rp, ci, v, 4096)
