@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--stream-stage", type=int, default=0,
                     help="SpMV: 0 auto, 1 direct word reads, 2 LDS ring")
+    ap.add_argument("--first-delta-column", action="store_true",
+                    help="first delta of a row is its column (the paper's form) instead of "
+                         "column - row + 2^29")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,7 +204,7 @@ def main():
     t0 = time.perf_counter()
     A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
                            waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu,
-                           stream_stage=args.stream_stage)
+                           stream_stage=args.stream_stage, first_delta_column=args.first_delta_column)
     enc_s = time.perf_counter() - t0
     info = A0.info()
     log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
@@ -251,6 +254,7 @@ def main():
                    "layout": {1: "row", 2: "nnz"}[info["layout"]], "lane_nnz": info["lane_nnz"],
                    "waves_per_wg": info["waves_per_wg"],
                    "stream_stage": {1: "direct", 2: "lds_ring"}[info["stream_stage"]],
+                   "first_delta": "column" if info["first_delta_column"] else "column - row + 2^29",
                    "copies_rotated": copies},
         "compressed_GBps": round(achieved, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,

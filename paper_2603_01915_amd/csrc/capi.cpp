@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <chrono>
 #include <string>
 #include <vector>
@@ -519,8 +520,7 @@ namespace {
 
 dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                            const int32_t *col_idx, const void *vals, dtans_dtype dtype,
-                           const dtans_encode_opts *opts, WordCoder coder, void *coder_ctx,
-                           dtans_matrix **out) {
+                           const dtans_encode_opts *opts, DeviceEncoder *dev, dtans_matrix **out) {
     if (!out) return set_err(DTANS_EINVAL, "out is null");
     *out = nullptr;
     dtans_encode_opts o;
@@ -568,7 +568,7 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
     if (p.layout == kLayoutNnz) p.lane_nnz = (uint32_t)T;
     dtans_matrix *h = new dtans_matrix();
-    std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c, coder, coder_ctx);
+    std::string err = encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, p, h->c, dev);
     if (!err.empty()) {
         delete h;
         return from_msg(err);
@@ -585,13 +585,14 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
 dtans_status dtans_encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                               const int32_t *col_idx, const void *vals, dtans_dtype dtype,
                               const dtans_encode_opts *opts, dtans_matrix **out) {
-    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, nullptr, nullptr, out);
+    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, nullptr, out);
 }
 
 dtans_status dtans_encode_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                                   const int32_t *col_idx, const void *vals, dtans_dtype dtype,
                                   const dtans_encode_opts *opts, void *stream, dtans_matrix **out) {
-    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, device_word_coder, stream, out);
+    std::unique_ptr<DeviceEncoder> dev(new_device_encoder(stream));
+    return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, dev.get(), out);
 }
 
 dtans_status dtans_save(const dtans_matrix *mat, const char *path) {

@@ -73,36 +73,48 @@ struct EncodeParams {
     int threads = 0;  // 0 = hardware concurrency
 };
 
-// The inputs of the word pass of every lane stream (the base pass, the digit
-// pass and the interleave of the words in the decoder's order, Sec. IV-B and
-// IV-E), for a coder other than the host's own loop.  Symbols are indices
-// into an alphabet; meta[s] = first logical slot of s | base of s << 16, and
-// slots[first + digit] is the physical slot of that digit.
-struct WordJob {
-    const Container *c;          // geometry: layout, lane_nnz, row_ptr, lanes, waves
-    const int32_t *dsym, *vsym;  // per nonzero (nnz each)
-    int32_t dpad, vpad;          // padding symbols
-    std::vector<uint32_t> dmeta, vmeta;
-    std::vector<uint16_t> dslots, vslots;
+// Count of one symbol key (histograms are sorted by key).
+struct KeyCount {
+    uint64_t key;
+    int64_t count;
 };
-// Fills words and word_off (num_waves + 1 entries) exactly as the host loop
-// would; returns an empty string or an error message.
-typedef std::string (*WordCoder)(const WordJob &job, void *ctx, std::vector<uint32_t> &words,
-                                 std::vector<uint64_t> &word_off);
 
-// The word pass on the current GPU (encode_kernels.hip); ctx is the
-// hipStream_t to run on.  Blocks until the words are back on the host.
-std::string device_word_coder(const WordJob &job, void *ctx, std::vector<uint32_t> &words,
-                              std::vector<uint64_t> &word_off);
+// The alphabets as the per-nonzero passes need them: an open-addressing map
+// key -> symbol index (hkey / hval, hval -1 = empty, multiplicative hash of
+// SlotMap::lookup; keys not found are the escape symbol esc), meta[s] = first
+// logical slot of s | base of s << 16, slots[first + digit] = physical slot
+// of that digit, and the padding symbol.
+struct AlphabetMap {
+    std::vector<uint64_t> hkey;
+    std::vector<int32_t> hval;
+    int32_t esc = -1, pad = -1;
+    std::vector<uint32_t> meta;
+    std::vector<uint16_t> slots;
+};
+
+// The per-nonzero passes of the encoder on a device (encode_kernels.hip):
+// keys forms the delta and value keys of every nonzero of the validated
+// input (Container geometry already set) and returns both histograms;
+// streams then maps every nonzero to its symbols and writes the words and
+// escape regions of every wave, with their offsets, into the container
+// (Sec. IV-B, IV-E, IV-F), exactly as the host passes would.
+class DeviceEncoder {
+  public:
+    virtual ~DeviceEncoder() {}
+    virtual std::string keys(const Container &c, const int32_t *col, const void *vals,
+                             std::vector<KeyCount> &dhist, std::vector<KeyCount> &vhist) = 0;
+    virtual std::string streams(const AlphabetMap &d, const AlphabetMap &v, Container &c) = 0;
+};
+// A DeviceEncoder on the current GPU running on `stream` (a hipStream_t).
+DeviceEncoder *new_device_encoder(void *stream);
 
 // All functions return an empty string on success or an error message whose
 // first word is the error class ("EINVAL: ...", "ERANGE: ...", ...).
-// With `coder`, the words are made by it (escapes, tables and offsets of the
-// escape regions still on the host).
+// With `dev`, the per-nonzero passes run there (validation, the alphabet
+// fit and the tables stay on the host).
 std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col, const void *vals, uint32_t dtype,
-                       const EncodeParams &p, Container &out, WordCoder coder = nullptr,
-                       void *coder_ctx = nullptr);
+                       const EncodeParams &p, Container &out, DeviceEncoder *dev = nullptr);
 std::string save_container(const Container &c, const std::string &path);
 std::string load_container(const std::string &path, Container &c);
 // Full host decode with the kernels' integer arithmetic; fills col / vals

@@ -1,19 +1,22 @@
-// Device word pass of the CSR-dtANS encoder for gfx950: for every lane
-// stream the base pass (which steps load a word after each digit group) and
-// the digit pass (the slots of every segment and the words they pack into,
-// Sec. IV-E), and the interleave of the 64 lane streams of a wave in the
-// order the decoder's ballots consume them (Sec. IV-B).  The host fits the
-// alphabets, builds the tables, maps every nonzero to its two symbols and
-// writes the escape regions; this pass produces the words and the per-wave
-// word offsets, identical to the host encoder's.
+// The per-nonzero passes of the CSR-dtANS encoder on gfx950
+// (DeviceEncoder): delta and value keys of every nonzero (Sec. IV-A), their
+// histograms (radix sort + run-length encoding), the symbol of every nonzero
+// (the host's hash map, probed the same way), and per wave the words (base
+// pass, digit pass, Sec. IV-E, interleaved in the order the decoder's ballots
+// consume them, Sec. IV-B) and the escape regions (Sec. IV-F).  The host
+// validates the input, fits the alphabets and builds the tables between the
+// two calls; the container is identical to the host encoder's.
 //
-// One wavefront encodes one wave; lane q holds lane stream 64 w + q.  Two
-// kernels: the first runs every lane's base pass forward, keeps its load
-// flags (2 bits per step) and sums the wave's word count; the host turns the
-// counts into offsets; the second runs the digit pass backward from the
-// wave's last step, placing each step's words at the end of what is left of
-// the wave's region, and finally the three initial words of every lane.
+// Words: one wavefront encodes one wave; lane q holds lane stream 64 w + q.
+// enc_count_kernel runs every lane's base pass forward, keeps its load flags
+// (2 bits per step) and sums the wave's word count; the host turns the counts
+// into offsets; enc_words_kernel runs the digit pass backward from the wave's
+// last step, placing each step's words at the end of what is left of the
+// wave's region, and finally the three initial words of every lane.  Escapes
+// take the same count / offsets / write scheme, forward.
 #include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <string>
@@ -192,7 +195,136 @@ __global__ __launch_bounds__(256) void enc_words_kernel(WordJobDev J) {
     }
 }
 
-// device buffers of one coder call, freed on every path
+// Delta key of every nonzero g (Sec. IV-A): the difference to the previous
+// column, except at the start of a row or of a lane stream, where it is the
+// column relative to first_base of the row holding g.  The row is found by a
+// binary search of row_ptr (the last i with row_ptr[i] <= g).
+__global__ __launch_bounds__(256) void enc_keys_kernel(const int32_t *__restrict__ row_ptr, int64_t m,
+                                                       const int32_t *__restrict__ col, int64_t nnz,
+                                                       int32_t layout, int32_t lane_nnz, uint32_t first_mode,
+                                                       uint32_t *__restrict__ dkey) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nnz;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = m;  // row_ptr[lo] <= g < row_ptr[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (row_ptr[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const bool row_start = row_ptr[lo] == g;
+        const bool lane_start = layout == (int32_t)kLayoutRow ? row_start : g % lane_nnz == 0;
+        const uint32_t c = (uint32_t)col[g];
+        dkey[g] = (row_start || lane_start) ? c - first_base(first_mode, (uint32_t)lo)
+                                            : c - (uint32_t)col[g - 1];
+    }
+}
+
+struct DevAlphabet {
+    const uint64_t *hkey;
+    const int32_t *hval;
+    uint64_t mask;
+    int32_t esc;
+};
+
+__device__ __forceinline__ int32_t lookup(const DevAlphabet &a, uint64_t key) {
+    uint64_t h = ((key * 0x9e3779b97f4a7c15ull) >> 40) & a.mask;
+    while (a.hval[h] >= 0) {  // the map always has empty entries
+        if (a.hkey[h] == key) return a.hval[h];
+        h = (h + 1) & a.mask;
+    }
+    return a.esc;
+}
+
+template <typename VK>
+__global__ __launch_bounds__(256) void enc_lookup_kernel(const uint32_t *__restrict__ dkey,
+                                                         const VK *__restrict__ vkey, int64_t nnz,
+                                                         DevAlphabet da, DevAlphabet va,
+                                                         int32_t *__restrict__ dsym, int32_t *__restrict__ vsym) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nnz;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        dsym[g] = lookup(da, dkey[g]);
+        vsym[g] = lookup(va, (uint64_t)vkey[g]);
+    }
+}
+
+// escaped deltas and values of every wave (counts, then the regions in the
+// decoder's order: segment j, its nonzero k, then lane)
+struct EscJob {
+    const int32_t *row_ptr;
+    const int32_t *dsym, *vsym;
+    const uint32_t *dkey;
+    const void *vals;
+    int32_t desc, vesc, f64;
+    int64_t nnz, num_lanes, num_waves;
+    int32_t layout, lane_nnz;
+    uint64_t *dcount, *vcount;           // per wave (count kernel)
+    const uint64_t *doff, *voff;         // num_waves + 1 (write kernel)
+    uint32_t *escd;
+    uint64_t *escv;
+    int32_t *err;
+};
+
+__device__ __forceinline__ void esc_span(const EscJob &J, int64_t l, int64_t &g0, int64_t &cnt) {
+    g0 = 0;
+    cnt = 0;
+    if (l >= J.num_lanes) return;
+    if (J.layout == (int32_t)kLayoutRow) {
+        g0 = J.row_ptr[l];
+        cnt = (int64_t)J.row_ptr[l + 1] - g0;
+    } else {
+        g0 = l * (int64_t)J.lane_nnz;
+        cnt = std::min<int64_t>(J.lane_nnz, J.nnz - g0);
+    }
+}
+
+__global__ __launch_bounds__(256) void enc_esc_count_kernel(EscJob J) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= J.num_waves) return;
+    const uint32_t q = threadIdx.x & 63u;
+    int64_t g0, cnt;
+    esc_span(J, w * 64 + q, g0, cnt);
+    uint64_t nd = 0, nv = 0;
+    for (int64_t i = 0; i < cnt; ++i) {
+        nd += J.dsym[g0 + i] == J.desc;
+        nv += J.vsym[g0 + i] == J.vesc;
+    }
+    nd = wave_sum(nd);
+    nv = wave_sum(nv);
+    if (q == 0) {
+        J.dcount[w] = nd;
+        J.vcount[w] = nv;
+    }
+}
+
+__global__ __launch_bounds__(256) void enc_esc_write_kernel(EscJob J) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= J.num_waves) return;
+    const uint32_t q = threadIdx.x & 63u;
+    int64_t g0, cnt;
+    esc_span(J, w * 64 + q, g0, cnt);
+    const int64_t maxS = wave_max((cnt + 3) >> 2);
+    uint64_t pd = J.doff[w], pv = J.voff[w];
+    const uint64_t ed = J.doff[w + 1], ev = J.voff[w + 1];
+    for (int64_t t = 0; t < 4 * maxS; ++t) {  // t = 4 j + k
+        const bool live = t < cnt;
+        const bool fd = live && J.dsym[g0 + t] == J.desc;
+        const bool fv = live && J.vsym[g0 + t] == J.vesc;
+        const uint64_t md = wave_ballot(fd), mv = wave_ballot(fv);
+        const uint64_t nd = (uint64_t)__popcll(md), nv = (uint64_t)__popcll(mv);
+        if (pd + nd > ed || pv + nv > ev) {  // uniform; never expected
+            if (q == 0) atomicOr(J.err, 1);
+            return;
+        }
+        if (fd) J.escd[pd + prefix_below(md)] = J.dkey[g0 + t];
+        if (fv)
+            J.escv[pv + prefix_below(mv)] = J.f64 ? ((const uint64_t *)J.vals)[g0 + t]
+                                                  : (uint64_t)((const uint32_t *)J.vals)[g0 + t];
+        pd += nd;
+        pv += nv;
+    }
+}
+
+// device buffers of one encoder, freed with it
 struct DevBuffers {
     std::vector<void *> ptrs;
     ~DevBuffers() {
@@ -213,27 +345,105 @@ std::string hip_fail(hipError_t e, const char *what) {
     return std::string(e == hipErrorOutOfMemory ? "ENOMEM: " : "EHIP: ") + what + ": " + hipGetErrorString(e);
 }
 
-}  // namespace
-
-#define ENC_TRY(call)                                  \
-    do {                                               \
-        hipError_t e_ = (call);                        \
+#define ENC_TRY(call)                                     \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
-// WordCoder on the current device; ctx is the hipStream_t to run on.
-std::string device_word_coder(const WordJob &job, void *ctx, std::vector<uint32_t> &words,
-                              std::vector<uint64_t> &word_off) {
-    const Container &c = *job.c;
-    hipStream_t st = (hipStream_t)ctx;
-    const int64_t W = c.num_waves;
-    words.clear();
-    word_off.assign(W + 1, 0);
+unsigned elem_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
+
+// sorted (key, count) pairs of n keys of type K on the device
+template <typename K>
+std::string device_histogram(const K *keys, int64_t n, hipStream_t st, std::vector<KeyCount> &out) {
+    out.clear();
+    if (n == 0) return "";
+    DevBuffers B;
+    K *sorted = nullptr, *uniq = nullptr;
+    int32_t *counts = nullptr, *runs = nullptr;
+    ENC_TRY(B.alloc(sorted, n));
+    ENC_TRY(B.alloc(uniq, n));
+    ENC_TRY(B.alloc(counts, n));
+    ENC_TRY(B.alloc(runs, 1));
+    size_t a = 0, b = 0;
+    ENC_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, a, keys, sorted, (int)n, 0, (int)(8 * sizeof(K)), st));
+    ENC_TRY(hipcub::DeviceRunLengthEncode::Encode(nullptr, b, sorted, uniq, counts, runs, (int)n, st));
+    uint8_t *tmp = nullptr;
+    ENC_TRY(B.alloc(tmp, std::max(a, b)));
+    size_t ta = std::max(a, b), tb = ta;
+    ENC_TRY(hipcub::DeviceRadixSort::SortKeys(tmp, ta, keys, sorted, (int)n, 0, (int)(8 * sizeof(K)), st));
+    ENC_TRY(hipcub::DeviceRunLengthEncode::Encode(tmp, tb, sorted, uniq, counts, runs, (int)n, st));
+    int32_t nr = 0;
+    ENC_TRY(hipMemcpyAsync(&nr, runs, 4, hipMemcpyDeviceToHost, st));
+    ENC_TRY(hipStreamSynchronize(st));
+    if (nr < 0 || nr > n) return "ECORRUPT: device histogram";
+    std::vector<K> hk(nr);
+    std::vector<int32_t> hc(nr);
+    if (nr) {
+        ENC_TRY(hipMemcpyAsync(hk.data(), uniq, nr * sizeof(K), hipMemcpyDeviceToHost, st));
+        ENC_TRY(hipMemcpyAsync(hc.data(), counts, nr * 4, hipMemcpyDeviceToHost, st));
+        ENC_TRY(hipStreamSynchronize(st));
+    }
+    out.resize(nr);
+    for (int32_t i = 0; i < nr; ++i) out[i] = {(uint64_t)hk[i], (int64_t)hc[i]};
+    return "";
+}
+
+class GpuEncoder final : public DeviceEncoder {
+  public:
+    explicit GpuEncoder(void *stream) : st_((hipStream_t)stream) {}
+
+    std::string keys(const Container &c, const int32_t *col, const void *vals, std::vector<KeyCount> &dhist,
+                     std::vector<KeyCount> &vhist) override {
+        const int64_t nnz = c.nnz;
+        f64_ = c.dtype == kF64;
+        const size_t vb = f64_ ? 8 : 4;
+        ENC_TRY(B_.alloc(rp_, c.row_ptr.size()));
+        ENC_TRY(B_.alloc(col_, nnz));
+        ENC_TRY(B_.alloc(vals_, nnz * vb));
+        ENC_TRY(B_.alloc(dkey_, nnz));
+        ENC_TRY(hipMemcpyAsync(rp_, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st_));
+        if (nnz) {
+            ENC_TRY(hipMemcpyAsync(col_, col, nnz * 4, hipMemcpyHostToDevice, st_));
+            ENC_TRY(hipMemcpyAsync(vals_, vals, nnz * vb, hipMemcpyHostToDevice, st_));
+            hipLaunchKernelGGL(enc_keys_kernel, dim3(elem_grid(nnz)), dim3(256), 0, st_, rp_, c.m, col_, nnz,
+                               (int32_t)c.layout, (int32_t)c.lane_nnz, c.first_mode, dkey_);
+            ENC_TRY(hipGetLastError());
+        }
+        std::string e = device_histogram(dkey_, nnz, st_, dhist);
+        if (!e.empty()) return e;
+        if (f64_) return device_histogram((const uint64_t *)vals_, nnz, st_, vhist);
+        return device_histogram((const uint32_t *)vals_, nnz, st_, vhist);
+    }
+
+    std::string streams(const AlphabetMap &da, const AlphabetMap &va, Container &c) override;
+
+  private:
+    hipStream_t st_;
+    DevBuffers B_;
+    bool f64_ = false;
+    int32_t *rp_ = nullptr, *col_ = nullptr;
+    uint8_t *vals_ = nullptr;
+    uint32_t *dkey_ = nullptr;
+};
+
+std::string GpuEncoder::streams(const AlphabetMap &da, const AlphabetMap &va, Container &c) {
+    const int64_t W = c.num_waves, nnz = c.nnz;
+    c.words.clear();
+    c.escd.clear();
+    c.escv.clear();
+    c.word_off.assign(W + 1, 0);
+    c.escd_off.assign(W + 1, 0);
+    c.escv_off.assign(W + 1, 0);
     if (W == 0) return "";
     auto in_range = [](int32_t s, size_t n) { return s >= 0 && (size_t)s < n; };
-    if (c.nnz > 0 && (!in_range(job.dpad, job.dmeta.size()) || !in_range(job.vpad, job.vmeta.size())))
+    if (nnz > 0 && (!in_range(da.pad, da.meta.size()) || !in_range(va.pad, va.meta.size())))
         return "EUNSUPPORTED: an alphabet without a padding symbol";
-    // flag words per wave: 64 lanes x ceil((steps) / 16), steps = maxS - 1
+    for (const AlphabetMap *a : {&da, &va}) {
+        const size_t h = a->hkey.size();
+        if (h == 0 || (h & (h - 1)) || a->hval.size() != h) return "ECORRUPT: bad symbol map";
+    }
+    // flag words per wave: 64 lanes x ceil(steps / 16), steps = maxS - 1
     std::vector<uint64_t> flag_off(W + 1, 0);
     for (int64_t w = 0; w < W; ++w) {
         int64_t maxS = 0;
@@ -247,38 +457,58 @@ std::string device_word_coder(const WordJob &job, void *ctx, std::vector<uint32_
         const int64_t steps = maxS > 0 ? maxS - 1 : 0;
         flag_off[w + 1] = flag_off[w] + 64 * (uint64_t)((steps + 15) / 16);
     }
-    const size_t nnz = (size_t)c.nnz;
     DevBuffers B;
-    WordJobDev J = {};
-    int32_t *rp = nullptr, *ds = nullptr, *vs = nullptr, *err = nullptr;
-    uint32_t *dm = nullptr, *vm = nullptr, *fl = nullptr, *wd = nullptr;
+    int32_t *ds = nullptr, *vs = nullptr, *err = nullptr, *dhv = nullptr, *vhv = nullptr;
+    uint32_t *dm = nullptr, *vm = nullptr, *fl = nullptr, *wd = nullptr, *escd = nullptr;
     uint16_t *dsl = nullptr, *vsl = nullptr;
-    uint64_t *fo = nullptr, *ww = nullptr, *wo = nullptr;
-    const bool row = c.layout == kLayoutRow;
-    ENC_TRY(B.alloc(rp, row ? c.row_ptr.size() : 1));
+    uint64_t *fo = nullptr, *ww = nullptr, *wo = nullptr, *dhk = nullptr, *vhk = nullptr;
+    uint64_t *dc = nullptr, *vc = nullptr, *doff = nullptr, *voff = nullptr, *escv = nullptr;
     ENC_TRY(B.alloc(ds, nnz));
     ENC_TRY(B.alloc(vs, nnz));
-    ENC_TRY(B.alloc(dm, job.dmeta.size()));
-    ENC_TRY(B.alloc(vm, job.vmeta.size()));
-    ENC_TRY(B.alloc(dsl, job.dslots.size()));
-    ENC_TRY(B.alloc(vsl, job.vslots.size()));
+    ENC_TRY(B.alloc(dhk, da.hkey.size()));
+    ENC_TRY(B.alloc(vhk, va.hkey.size()));
+    ENC_TRY(B.alloc(dhv, da.hval.size()));
+    ENC_TRY(B.alloc(vhv, va.hval.size()));
+    ENC_TRY(B.alloc(dm, da.meta.size()));
+    ENC_TRY(B.alloc(vm, va.meta.size()));
+    ENC_TRY(B.alloc(dsl, da.slots.size()));
+    ENC_TRY(B.alloc(vsl, va.slots.size()));
     ENC_TRY(B.alloc(fo, W + 1));
     ENC_TRY(B.alloc(fl, flag_off[W]));
     ENC_TRY(B.alloc(ww, W));
     ENC_TRY(B.alloc(wo, W + 1));
+    ENC_TRY(B.alloc(dc, W));
+    ENC_TRY(B.alloc(vc, W));
+    ENC_TRY(B.alloc(doff, W + 1));
+    ENC_TRY(B.alloc(voff, W + 1));
     ENC_TRY(B.alloc(err, 1));
-    if (row) ENC_TRY(hipMemcpyAsync(rp, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st));
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_) : hipSuccess;
+    };
+    ENC_TRY(up(dhk, da.hkey.data(), da.hkey.size() * 8));
+    ENC_TRY(up(vhk, va.hkey.data(), va.hkey.size() * 8));
+    ENC_TRY(up(dhv, da.hval.data(), da.hval.size() * 4));
+    ENC_TRY(up(vhv, va.hval.data(), va.hval.size() * 4));
+    ENC_TRY(up(dm, da.meta.data(), da.meta.size() * 4));
+    ENC_TRY(up(vm, va.meta.data(), va.meta.size() * 4));
+    ENC_TRY(up(dsl, da.slots.data(), da.slots.size() * 2));
+    ENC_TRY(up(vsl, va.slots.data(), va.slots.size() * 2));
+    ENC_TRY(up(fo, flag_off.data(), (W + 1) * 8));
+    ENC_TRY(hipMemsetAsync(err, 0, 4, st_));
+    // symbols
     if (nnz) {
-        ENC_TRY(hipMemcpyAsync(ds, job.dsym, nnz * 4, hipMemcpyHostToDevice, st));
-        ENC_TRY(hipMemcpyAsync(vs, job.vsym, nnz * 4, hipMemcpyHostToDevice, st));
+        const DevAlphabet dA = {dhk, dhv, da.hkey.size() - 1, da.esc}, vA = {vhk, vhv, va.hkey.size() - 1, va.esc};
+        if (f64_)
+            hipLaunchKernelGGL(enc_lookup_kernel<uint64_t>, dim3(elem_grid(nnz)), dim3(256), 0, st_, dkey_,
+                               (const uint64_t *)vals_, nnz, dA, vA, ds, vs);
+        else
+            hipLaunchKernelGGL(enc_lookup_kernel<uint32_t>, dim3(elem_grid(nnz)), dim3(256), 0, st_, dkey_,
+                               (const uint32_t *)vals_, nnz, dA, vA, ds, vs);
+        ENC_TRY(hipGetLastError());
     }
-    ENC_TRY(hipMemcpyAsync(dm, job.dmeta.data(), job.dmeta.size() * 4, hipMemcpyHostToDevice, st));
-    ENC_TRY(hipMemcpyAsync(vm, job.vmeta.data(), job.vmeta.size() * 4, hipMemcpyHostToDevice, st));
-    ENC_TRY(hipMemcpyAsync(dsl, job.dslots.data(), job.dslots.size() * 2, hipMemcpyHostToDevice, st));
-    ENC_TRY(hipMemcpyAsync(vsl, job.vslots.data(), job.vslots.size() * 2, hipMemcpyHostToDevice, st));
-    ENC_TRY(hipMemcpyAsync(fo, flag_off.data(), (W + 1) * 8, hipMemcpyHostToDevice, st));
-    ENC_TRY(hipMemsetAsync(err, 0, 4, st));
-    J.row_ptr = rp;
+    // counts of words and escapes per wave
+    WordJobDev J = {};
+    J.row_ptr = rp_;
     J.dsym = ds;
     J.vsym = vs;
     J.dmeta = dm;
@@ -291,32 +521,80 @@ std::string device_word_coder(const WordJob &job, void *ctx, std::vector<uint32_
     J.word_off = wo;
     J.words = nullptr;
     J.err = err;
-    J.nnz = c.nnz;
+    J.nnz = nnz;
     J.num_lanes = c.num_lanes;
     J.num_waves = W;
     J.layout = (int32_t)c.layout;
     J.lane_nnz = (int32_t)c.lane_nnz;
-    J.dpad = job.dpad;
-    J.vpad = job.vpad;
+    J.dpad = da.pad;
+    J.vpad = va.pad;
+    EscJob E = {};
+    E.row_ptr = rp_;
+    E.dsym = ds;
+    E.vsym = vs;
+    E.dkey = dkey_;
+    E.vals = vals_;
+    E.desc = da.esc;
+    E.vesc = va.esc;
+    E.f64 = f64_ ? 1 : 0;
+    E.nnz = nnz;
+    E.num_lanes = c.num_lanes;
+    E.num_waves = W;
+    E.layout = (int32_t)c.layout;
+    E.lane_nnz = (int32_t)c.lane_nnz;
+    E.dcount = dc;
+    E.vcount = vc;
+    E.doff = doff;
+    E.voff = voff;
+    E.err = err;
     const dim3 grid((unsigned)((W + 3) / 4)), block(256);
-    hipLaunchKernelGGL(enc_count_kernel, grid, block, 0, st, J);
+    hipLaunchKernelGGL(enc_count_kernel, grid, block, 0, st_, J);
     ENC_TRY(hipGetLastError());
-    std::vector<uint64_t> counts(W);
-    ENC_TRY(hipMemcpyAsync(counts.data(), ww, W * 8, hipMemcpyDeviceToHost, st));
-    ENC_TRY(hipStreamSynchronize(st));
-    for (int64_t w = 0; w < W; ++w) word_off[w + 1] = word_off[w] + counts[w];
-    ENC_TRY(B.alloc(wd, word_off[W]));
+    hipLaunchKernelGGL(enc_esc_count_kernel, grid, block, 0, st_, E);
+    ENC_TRY(hipGetLastError());
+    std::vector<uint64_t> cw(W), cd(W), cv(W);
+    ENC_TRY(hipMemcpyAsync(cw.data(), ww, W * 8, hipMemcpyDeviceToHost, st_));
+    ENC_TRY(hipMemcpyAsync(cd.data(), dc, W * 8, hipMemcpyDeviceToHost, st_));
+    ENC_TRY(hipMemcpyAsync(cv.data(), vc, W * 8, hipMemcpyDeviceToHost, st_));
+    ENC_TRY(hipStreamSynchronize(st_));
+    for (int64_t w = 0; w < W; ++w) {
+        c.word_off[w + 1] = c.word_off[w] + cw[w];
+        c.escd_off[w + 1] = c.escd_off[w] + cd[w];
+        c.escv_off[w + 1] = c.escv_off[w] + cv[w];
+    }
+    ENC_TRY(B.alloc(wd, c.word_off[W]));
+    ENC_TRY(B.alloc(escd, c.escd_off[W]));
+    ENC_TRY(B.alloc(escv, c.escv_off[W]));
     J.words = wd;
-    ENC_TRY(hipMemcpyAsync(wo, word_off.data(), (W + 1) * 8, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(enc_words_kernel, grid, block, 0, st, J);
+    E.escd = escd;
+    E.escv = escv;
+    ENC_TRY(up(wo, c.word_off.data(), (W + 1) * 8));
+    ENC_TRY(up(doff, c.escd_off.data(), (W + 1) * 8));
+    ENC_TRY(up(voff, c.escv_off.data(), (W + 1) * 8));
+    hipLaunchKernelGGL(enc_words_kernel, grid, block, 0, st_, J);
     ENC_TRY(hipGetLastError());
-    words.resize(word_off[W]);
+    if (c.escd_off[W] + c.escv_off[W]) {
+        hipLaunchKernelGGL(enc_esc_write_kernel, grid, block, 0, st_, E);
+        ENC_TRY(hipGetLastError());
+    }
+    c.words.resize(c.word_off[W]);
+    c.escd.resize(c.escd_off[W]);
+    c.escv.resize(c.escv_off[W]);
+    auto down = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st_) : hipSuccess;
+    };
     int32_t herr = 0;
-    if (word_off[W]) ENC_TRY(hipMemcpyAsync(words.data(), wd, word_off[W] * 4, hipMemcpyDeviceToHost, st));
-    ENC_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
-    ENC_TRY(hipStreamSynchronize(st));
-    if (herr) return "ECORRUPT: device word pass: a wave's words do not fill its region";
+    ENC_TRY(down(c.words.data(), wd, c.words.size() * 4));
+    ENC_TRY(down(c.escd.data(), escd, c.escd.size() * 4));
+    ENC_TRY(down(c.escv.data(), escv, c.escv.size() * 8));
+    ENC_TRY(down(&herr, err, 4));
+    ENC_TRY(hipStreamSynchronize(st_));
+    if (herr) return "ECORRUPT: device encoder: a wave's words or escapes do not fill its region";
     return "";
 }
+
+}  // namespace
+
+DeviceEncoder *new_device_encoder(void *stream) { return new GpuEncoder(stream); }
 
 }  // namespace dtans

@@ -72,11 +72,6 @@ uint64_t fnv1a(const uint8_t *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
 }
 
 // --------------------------------------------------------------- histograms
-struct KeyCount {
-    uint64_t key;
-    int64_t count;
-};
-
 std::vector<KeyCount> histogram(const std::vector<uint64_t> &keys, int threads) {
     const int64_t n = (int64_t)keys.size();
     int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n / 65536 + 1));
@@ -385,7 +380,7 @@ struct WaveOut {
 // ---------------------------------------------------------------- encode
 std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col, const void *vals, uint32_t dtype,
-                       const EncodeParams &p, Container &c, WordCoder coder, void *coder_ctx) {
+                       const EncodeParams &p, Container &c, DeviceEncoder *dev) {
     if (m < 0 || n < 0 || nnz < 0) return fail("EINVAL", "negative size");
     if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31))
         return fail("ERANGE", "rows, columns and nonzeros must be below 2^31");
@@ -419,42 +414,74 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     c.num_waves = (c.num_lanes + kWave - 1) / kWave;
 
     // symbols: delta keys (with resets at row and lane starts) and value bits
-    std::vector<uint64_t> dkey(nnz), vkey(nnz);
-    std::vector<uint8_t> rowstart(nnz, 0);
-    for (int64_t i = 0; i < m; ++i)
-        if (row_ptr[i] < row_ptr[i + 1]) rowstart[row_ptr[i]] = 1;
-    parallel_chunks(c.num_lanes, threads, [&](int64_t b, int64_t e, int) {
-        for (int64_t l = b; l < e; ++l) {
-            int64_t g0, cnt;
-            c.lane_range(l, g0, cnt);
-            for (int64_t t = 0; t < cnt; ++t) {
-                int64_t g = g0 + t;
-                if (t == 0 || rowstart[g]) {
-                    const int64_t row = c.layout == kLayoutRow ? l : row_of(c.row_ptr, g);
-                    dkey[g] = (uint32_t)col[g] - first_base(c.first_mode, (uint32_t)row);
-                } else {
-                    dkey[g] = (uint64_t)(col[g] - col[g - 1]);
+    std::vector<uint64_t> dkey, vkey;
+    std::vector<KeyCount> dhist, vhist;
+    if (dev) {
+        std::string err = dev->keys(c, col, vals, dhist, vhist);
+        if (!err.empty()) return err;
+    } else {
+        dkey.resize(nnz);
+        vkey.resize(nnz);
+        std::vector<uint8_t> rowstart(nnz, 0);
+        for (int64_t i = 0; i < m; ++i)
+            if (row_ptr[i] < row_ptr[i + 1]) rowstart[row_ptr[i]] = 1;
+        parallel_chunks(c.num_lanes, threads, [&](int64_t b, int64_t e, int) {
+            for (int64_t l = b; l < e; ++l) {
+                int64_t g0, cnt;
+                c.lane_range(l, g0, cnt);
+                for (int64_t t = 0; t < cnt; ++t) {
+                    int64_t g = g0 + t;
+                    if (t == 0 || rowstart[g]) {
+                        const int64_t row = c.layout == kLayoutRow ? l : row_of(c.row_ptr, g);
+                        dkey[g] = (uint32_t)col[g] - first_base(c.first_mode, (uint32_t)row);
+                    } else {
+                        dkey[g] = (uint64_t)(col[g] - col[g - 1]);
+                    }
                 }
             }
-        }
-    });
-    parallel_chunks(nnz, threads, [&](int64_t b, int64_t e, int) {
-        if (dtype == kF64) {
-            const uint64_t *v = (const uint64_t *)vals;
-            for (int64_t g = b; g < e; ++g) vkey[g] = v[g];
-        } else {
-            const uint32_t *v = (const uint32_t *)vals;
-            for (int64_t g = b; g < e; ++g) vkey[g] = v[g];
-        }
-    });
-    Fit dfit = fit_alphabet(histogram(dkey, threads), 32, true, (int)p.max_mult);
-    Fit vfit = fit_alphabet(histogram(vkey, threads), dtype == kF64 ? 64 : 32, false, (int)p.max_mult);
+        });
+        parallel_chunks(nnz, threads, [&](int64_t b, int64_t e, int) {
+            if (dtype == kF64) {
+                const uint64_t *v = (const uint64_t *)vals;
+                for (int64_t g = b; g < e; ++g) vkey[g] = v[g];
+            } else {
+                const uint32_t *v = (const uint32_t *)vals;
+                for (int64_t g = b; g < e; ++g) vkey[g] = v[g];
+            }
+        });
+        dhist = histogram(dkey, threads);
+        vhist = histogram(vkey, threads);
+    }
+    Fit dfit = fit_alphabet(dhist, 32, true, (int)p.max_mult);
+    Fit vfit = fit_alphabet(vhist, dtype == kF64 ? 64 : 32, false, (int)p.max_mult);
     SlotMap dsm, vsm;
     build_table(dfit, p.seed, c.dtab, dsm);
     build_table(vfit, p.seed ^ 0xd1b54a32d192ed03ull, c.vtab, vsm);
     table_stats(dfit, nnz, c.dtab);
     table_stats(vfit, nnz, c.vtab);
     const int dpad = pad_symbol(c.dtab, dsm), vpad = pad_symbol(c.vtab, vsm);
+    if (dev) {
+        AlphabetMap da, va;
+        auto fill = [](const SlotMap &sm, int pad, AlphabetMap &a) {
+            a.hkey = sm.hkey;
+            a.hval = sm.hval;
+            a.esc = sm.esc_index;
+            a.pad = pad;
+            a.meta.resize(sm.mult.size());
+            for (size_t s = 0; s < sm.mult.size(); ++s)
+                a.meta[s] = (uint32_t)sm.first[s] | ((uint32_t)sm.mult[s] << 16);
+            a.slots = sm.slots;
+        };
+        fill(dsm, dpad, da);
+        fill(vsm, vpad, va);
+        std::string err = dev->streams(da, va, c);
+        if (!err.empty()) return err;
+        if (c.word_off.size() != (size_t)c.num_waves + 1 || c.word_off.back() != c.words.size() ||
+            c.escd_off.size() != (size_t)c.num_waves + 1 || c.escd_off.back() != c.escd.size() ||
+            c.escv_off.size() != (size_t)c.num_waves + 1 || c.escv_off.back() != c.escv.size())
+            return fail("ECORRUPT", "device encoder returned inconsistent offsets");
+        return "";
+    }
 
     // symbol indices per nonzero
     std::vector<int32_t> dsym(nnz), vsym(nnz);
@@ -484,8 +511,6 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
                 cnts[q] = 0;
                 if (l < c.num_lanes) c.lane_range(l, g0s[q], cnts[q]);
                 int64_t S = (cnts[q] + 3) / 4;
-                maxS = std::max(maxS, S);
-                if (coder) continue;
                 sym.resize(8 * S);
                 for (int64_t t = 0; t < 4 * S; ++t) {
                     if (t < cnts[q]) {
@@ -498,11 +523,12 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
                 }
                 lanes[q] = LaneCode();
                 encode_lane(sym.data(), S, dsm, vsm, lanes[q]);
+                maxS = std::max(maxS, S);
             }
-            for (int k = 0; k < 3 && !coder; ++k)
+            for (int k = 0; k < 3; ++k)
                 for (int q = 0; q < kWave; ++q)
                     if (lanes[q].S > 0) o.words.push_back(lanes[q].init[k]);
-            for (int64_t j = 0; j + 1 < maxS && !coder; ++j) {
+            for (int64_t j = 0; j + 1 < maxS; ++j) {
                 for (int q = 0; q < kWave; ++q)
                     if (j < lanes[q].S - 1 && lanes[q].load[2 * j]) o.words.push_back(lanes[q].w[3 * j]);
                 for (int q = 0; q < kWave; ++q)
@@ -543,26 +569,6 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     c.word_off.push_back(c.words.size());
     c.escd_off.push_back(c.escd.size());
     c.escv_off.push_back(c.escv.size());
-    if (coder) {
-        WordJob job;
-        job.c = &c;
-        job.dsym = dsym.data();
-        job.vsym = vsym.data();
-        job.dpad = dpad;
-        job.vpad = vpad;
-        auto meta = [](const SlotMap &sm, std::vector<uint32_t> &mt, std::vector<uint16_t> &sl) {
-            mt.resize(sm.mult.size());
-            for (size_t s = 0; s < sm.mult.size(); ++s)
-                mt[s] = (uint32_t)sm.first[s] | ((uint32_t)sm.mult[s] << 16);
-            sl = sm.slots;
-        };
-        meta(dsm, job.dmeta, job.dslots);
-        meta(vsm, job.vmeta, job.vslots);
-        std::string err = coder(job, coder_ctx, c.words, c.word_off);
-        if (!err.empty()) return err;
-        if (c.word_off.size() != (size_t)c.num_waves + 1 || c.word_off.back() != c.words.size())
-            return fail("ECORRUPT", "device word coder returned inconsistent offsets");
-    }
     return "";
 }
 

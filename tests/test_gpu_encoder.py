@@ -1,9 +1,10 @@
-"""The encoder's word pass on the GPU (dtans_encode_csr_gpu): every container
-is byte-identical to the host encoder's and decoded exactly by the oracle,
-over both layouts and value types, rows that are empty, duplicated, very
-long (many 16-step flag words) or escape-heavy, ragged last lanes and waves,
-degenerate sizes, the all-256-bases case where every check extracts, and the
-full-size stencil and pruned weight."""
+"""The encoder's per-nonzero passes on the GPU (dtans_encode_csr_gpu: keys,
+histograms, symbols, words, escape regions): every container is
+byte-identical to the host encoder's and decoded exactly by the oracle, over
+both layouts, value types and first-delta modes, rows that are empty,
+duplicated, very long (many 16-step flag words) or escape-heavy, ragged last
+lanes and waves, degenerate sizes, the all-256-bases case where every check
+extracts, and the full-size stencil and pruned weight."""
 import time
 
 import numpy as np
@@ -30,7 +31,7 @@ def rand_csr(m, n, dens, seed, dtype=np.float64, pool=None):
 
 
 def both(tmp_path, tag, rp, ci, v, n, **kw):
-    """Encode on the host and with the GPU word pass; the two files must be
+    """Encode on the host and with the GPU passes; the two files must be
     equal byte for byte, and the oracle must decode the GPU's exactly."""
     need_gpu()
     progress("encoder %s" % tag)
@@ -66,6 +67,25 @@ def test_adversarial_rows(tmp_path):
     v[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, 5e-324]
     for layout, T in LAYOUTS:
         both(tmp_path, "adv_%s_%d" % (layout, T), rp.astype(np.int32), ci, v, n, layout=layout, lane_nnz=T)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_escape_heavy(tmp_path, dtype):
+    """More distinct deltas and values than 4096 slots hold: thousands of
+    escapes of both kinds, in every layout and both first-delta modes."""
+    rng = np.random.default_rng(21)
+    m = 400
+    rows = [sorted(rng.choice(10 ** 7, size=rng.integers(0, 40), replace=False)) for _ in range(m)]
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], np.int64).astype(np.int32)
+    v = rng.standard_normal(len(ci)).astype(dtype)
+    for layout, T in (("row", 0), ("nnz", 8), ("nnz", 100)):
+        for fdc in (False, True):
+            B = both(tmp_path, "esc_%s_%d_%d" % (layout, T, fdc), rp.astype(np.int32), ci, v, 10 ** 7,
+                     layout=layout, lane_nnz=T, first_delta_column=fdc)
+            inf = B.info()
+            assert inf["esc_delta"] > 1000 and inf["esc_value"] > 1000
 
 
 def test_long_rows_many_flag_words(tmp_path):
