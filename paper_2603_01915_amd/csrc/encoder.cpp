@@ -390,16 +390,42 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
         return fail("EINVAL", "lane_nnz must be a positive multiple of 4");
     if (!row_ptr || (nnz > 0 && (!col || !vals))) return fail("EINVAL", "null array");
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail("EINVAL", "row_ptr must run from 0 to nnz");
-    for (int64_t i = 0; i < m; ++i)
-        if (row_ptr[i + 1] < row_ptr[i]) return fail("EINVAL", "row_ptr decreases at row " + std::to_string(i));
-    for (int64_t i = 0; i < m; ++i)
-        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
-            if (col[q] < 0 || col[q] >= n)
-                return fail("ERANGE", "column index out of range in row " + std::to_string(i));
-            if (q > row_ptr[i] && col[q] < col[q - 1])
-                return fail("EUNSORTED", "columns not ascending in row " + std::to_string(i));
-        }
     const int threads = thread_count(p.threads);
+    // checks in row chunks; the error reported is the one a serial scan finds
+    // first (the lowest failing row)
+    {
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads, m / 65536 + 1));
+        std::vector<int64_t> bad(T, -1);
+        parallel_chunks(m, T, [&](int64_t b, int64_t e, int t) {
+            for (int64_t i = b; i < e; ++i)
+                if (row_ptr[i + 1] < row_ptr[i]) {
+                    bad[t] = i;
+                    return;
+                }
+        });
+        for (int64_t i : bad)
+            if (i >= 0) return fail("EINVAL", "row_ptr decreases at row " + std::to_string(i));
+        std::vector<int64_t> brow(T, -1);
+        std::vector<int> bkind(T, 0);
+        parallel_chunks(m, T, [&](int64_t b, int64_t e, int t) {
+            for (int64_t i = b; i < e; ++i)
+                for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+                    const int kind = (col[q] < 0 || col[q] >= n) ? 1
+                                     : (q > row_ptr[i] && col[q] < col[q - 1]) ? 2 : 0;
+                    if (kind) {
+                        brow[t] = i;
+                        bkind[t] = kind;
+                        return;
+                    }
+                }
+        });
+        for (int t = 0; t < T; ++t) {
+            if (brow[t] < 0) continue;
+            if (bkind[t] == 1)
+                return fail("ERANGE", "column index out of range in row " + std::to_string(brow[t]));
+            return fail("EUNSORTED", "columns not ascending in row " + std::to_string(brow[t]));
+        }
+    }
     c = Container();
     c.dtype = dtype;
     c.layout = p.layout;
