@@ -413,10 +413,11 @@ def bench_autograd(args, torch, P):
 
 
 def bench_encode(args, torch, P):
-    """Encoding throughput (nonzeros per second, host CSR arrays in, host
-    container out) of dtans_encode_csr and dtans_encode_csr_gpu, whose
+    """Encoding throughput (nonzeros per second, CSR arrays in, host
+    container out) of dtans_encode_csr and dtans_encode_csr_gpu (host arrays)
+    and dtans_encode_csr_device (arrays already in device memory), whose
     containers are identical; each is the best of `steps` (at most 5) calls.
-    The GPU call includes its uploads, the word pass and the download."""
+    The GPU calls include their uploads and downloads."""
     import workloads
 
     steps = max(1, min(args.steps, 5))
@@ -427,23 +428,31 @@ def bench_encode(args, torch, P):
     cases.append(("pruned 11008x4096 fp32, nnz layout", rp, ci, v, 4096, "auto"))
     out = []
     for name, rp, ci, v, n, layout in cases:
+        drp = torch.from_numpy(np.ascontiguousarray(rp, np.int32)).cuda()
+        dci = torch.from_numpy(np.ascontiguousarray(ci, np.int32)).cuda()
+        dv = torch.from_numpy(np.ascontiguousarray(v)).cuda()
         times = {}
-        for gpu in (False, True):
+        for mode in ("host", "gpu", "device"):
             best = None
-            for _ in range(steps + (1 if gpu else 0)):  # one untimed GPU call first
+            for _ in range(steps + (0 if mode == "host" else 1)):  # one untimed GPU call first
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, gpu_encode=gpu)
+                if mode == "device":
+                    A = P.Matrix.from_csr_device(drp, dci, dv, n, layout=layout)
+                else:
+                    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, gpu_encode=mode == "gpu")
                 dt = time.perf_counter() - t0
                 A.close()
                 best = dt if best is None else min(best, dt)
-            times[gpu] = best
-            log("%s: %s encoder %.3f s" % (name, "GPU" if gpu else "host", best))
-        out.append({"workload": name, "nnz": len(ci), "host_s": round(times[False], 4),
-                    "gpu_s": round(times[True], 4),
-                    "host_Mnnz_per_s": round(len(ci) / times[False] / 1e6, 1),
-                    "gpu_Mnnz_per_s": round(len(ci) / times[True] / 1e6, 1),
-                    "speedup": round(times[False] / times[True], 3)})
+            times[mode] = best
+            log("%s: %s encoder %.3f s" % (name, mode, best))
+        del drp, dci, dv
+        out.append({"workload": name, "nnz": len(ci), "host_s": round(times["host"], 4),
+                    "gpu_s": round(times["gpu"], 4), "gpu_device_inputs_s": round(times["device"], 4),
+                    "host_Mnnz_per_s": round(len(ci) / times["host"] / 1e6, 1),
+                    "gpu_Mnnz_per_s": round(len(ci) / times["gpu"] / 1e6, 1),
+                    "gpu_device_inputs_Mnnz_per_s": round(len(ci) / times["device"] / 1e6, 1),
+                    "speedup": round(times["host"] / times["gpu"], 3)})
     res = {"metric": "encode throughput (host CSR arrays to container)", "value": out[0]["gpu_Mnnz_per_s"],
            "unit": "Mnnz/s", "n_gpus": 1, "steps": steps, "warmup": 1,
            "ms_per_step": round(out[0]["gpu_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",

@@ -143,6 +143,20 @@ dtans_status dtans_encode_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int32
                                   const int32_t *col_idx, const void *vals, dtans_dtype dtype,
                                   const dtans_encode_opts *opts, void *stream, dtans_matrix **out);
 
+/*
+ * As dtans_encode_csr_gpu, for CSR arrays already in device memory (e.g. a
+ * weight re-encoded after pruning): row_ptr, col_idx and vals are DEVICE
+ * pointers, read on `stream` (they must stay valid and unchanged until the
+ * call returns).  row_ptr is copied to the host (the container keeps it);
+ * columns are checked on the device with the same error classes and rows as
+ * dtans_encode_csr (DTANS_ERANGE / DTANS_EUNSORTED for the first failing row).
+ * opts->sort_rows is not supported here (DTANS_EUNSUPPORTED).  The container
+ * is byte-identical to dtans_encode_csr's on the same arrays.
+ */
+dtans_status dtans_encode_csr_device(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                                     const dtans_encode_opts *opts, void *stream, dtans_matrix **out);
+
 /* Write / read the container file (Sec. II-A: the encoded matrix can be kept
  * for repeated decoding).  dtans_load checks the checksum and structure and
  * verifies by a full host decode before returning a handle. */

@@ -83,6 +83,22 @@ def _ld(t) -> int:
     return max(int(t.stride(0)), int(t.size(1)), 1)
 
 
+def _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, stream_stage, max_mult,
+                 first_delta_column) -> EncodeOpts:
+    o = EncodeOpts()
+    L.dtans_default_opts(ctypes.byref(o))
+    o.layout = _LAYOUTS[layout]
+    o.lane_nnz = lane_nnz
+    o.waves_per_wg = waves_per_wg
+    o.wg_per_cu = wg_per_cu
+    o.sort_rows = int(bool(sort_rows))
+    o.perm_seed = seed
+    o.stream_stage = stream_stage
+    o.max_mult = max_mult
+    o.first_delta_column = int(bool(first_delta_column))
+    return o
+
+
 class Matrix:
     """A CSR matrix encoded in CSR-dtANS (host container + device copy)."""
 
@@ -101,9 +117,9 @@ class Matrix:
                  seed: int = 1, stream_stage: int = 0, max_mult: int = 0,
                  first_delta_column: bool = False, gpu_encode: bool = False,
                  stream=None) -> "Matrix":
-        """Encode host CSR arrays.  ``gpu_encode`` runs the streams' base and
-        digit passes and the word interleave on the current GPU (the same
-        container as the host encoder's)."""
+        """Encode host CSR arrays.  ``gpu_encode`` runs every pass over the
+        nonzeros (keys, histograms, symbols, words, escapes) on the current
+        GPU; the container is the same as the host encoder's."""
         L = _lib.load()
         rp = _np(row_ptr, np.int32)
         ci = _np(col, np.int32)
@@ -111,17 +127,8 @@ class Matrix:
         if v.dtype not in (np.float32, np.float64):
             v = v.astype(np.float64)
         m, nnz = len(rp) - 1, len(ci)
-        o = EncodeOpts()
-        L.dtans_default_opts(ctypes.byref(o))
-        o.layout = _LAYOUTS[layout]
-        o.lane_nnz = lane_nnz
-        o.waves_per_wg = waves_per_wg
-        o.wg_per_cu = wg_per_cu
-        o.sort_rows = int(bool(sort_rows))
-        o.perm_seed = seed
-        o.stream_stage = stream_stage
-        o.max_mult = max_mult
-        o.first_delta_column = int(bool(first_delta_column))
+        o = _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, stream_stage,
+                         max_mult, first_delta_column)
         h = ctypes.c_void_p()
         if gpu_encode:
             _lib.check(L.dtans_encode_csr_gpu(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
@@ -129,6 +136,34 @@ class Matrix:
         else:
             _lib.check(L.dtans_encode_csr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),
                                           ctypes.byref(o), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_csr_device(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
+                        waves_per_wg: int = 0, wg_per_cu: int = 0, seed: int = 1, stream_stage: int = 0,
+                        max_mult: int = 0, first_delta_column: bool = False, stream=None) -> "Matrix":
+        """Encode CSR arrays already in device memory: contiguous 1-D CUDA
+        tensors, row_ptr and col int32, vals float32 or float64.  The passes
+        over the nonzeros run on the GPU (on `stream`, default the current
+        one); the container is the same as the host encoder's."""
+        torch = _torch()
+        for t, name in ((row_ptr, "row_ptr"), (col, "col"), (vals, "vals")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dim() != 1 or not t.is_contiguous():
+                raise TypeError("%s must be a contiguous 1-D CUDA tensor" % name)
+        if row_ptr.dtype != torch.int32 or col.dtype != torch.int32:
+            raise TypeError("row_ptr and col must be int32")
+        if vals.dtype not in (torch.float32, torch.float64):
+            raise TypeError("vals must be float32 or float64")
+        if col.numel() != vals.numel() or row_ptr.numel() < 1:
+            raise ValueError("col and vals must have nnz entries, row_ptr m + 1")
+        L = _lib.load()
+        o = _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, False, seed, stream_stage, max_mult,
+                         first_delta_column)
+        code = _lib.F64 if vals.dtype == torch.float64 else _lib.F32
+        h = ctypes.c_void_p()
+        _lib.check(L.dtans_encode_csr_device(row_ptr.numel() - 1, n, col.numel(), row_ptr.data_ptr(),
+                                             col.data_ptr(), vals.data_ptr(), code, ctypes.byref(o),
+                                             _stream(stream), ctypes.byref(h)))
         return cls(h.value)
 
     @classmethod

@@ -67,6 +67,8 @@ SIGNATURES = {
     "dtans_encode_csr": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, ctypes.POINTER(EncodeOpts), _PP]),
     "dtans_encode_csr_gpu": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, ctypes.POINTER(EncodeOpts), _P,
                                   _PP]),
+    "dtans_encode_csr_device": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, ctypes.POINTER(EncodeOpts),
+                                       _P, _PP]),
     "dtans_save": (_I32, [_P, _S]),
     "dtans_load": (_I32, [_S, _PP]),
     "dtans_to_device": (_I32, [_P, _P]),

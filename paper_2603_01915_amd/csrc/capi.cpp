@@ -595,6 +595,24 @@ dtans_status dtans_encode_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int32
     return encode_common(m, n, nnz, row_ptr, col_idx, vals, dtype, opts, dev.get(), out);
 }
 
+dtans_status dtans_encode_csr_device(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                                     const dtans_encode_opts *opts, void *stream, dtans_matrix **out) {
+    if (!out) return set_err(DTANS_EINVAL, "out is null");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0) return set_err(DTANS_EINVAL, "negative size");
+    if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31))
+        return set_err(DTANS_ERANGE, "rows, columns and nonzeros must be below 2^31");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null array");
+    if (opts && opts->sort_rows) return set_err(DTANS_EUNSUPPORTED, "sort_rows needs host arrays");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> rp(m + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::unique_ptr<DeviceEncoder> dev(new_device_encoder(stream, true));
+    return encode_common(m, n, nnz, rp.data(), col_idx, vals, dtype, opts, dev.get(), out);
+}
+
 dtans_status dtans_save(const dtans_matrix *mat, const char *path) {
     if (!mat || !path) return set_err(DTANS_EINVAL, "null argument");
     return from_msg(save_container(mat->c, path));

@@ -93,8 +93,11 @@ struct AlphabetMap {
 };
 
 // The per-nonzero passes of the encoder on a device (encode_kernels.hip):
-// keys forms the delta and value keys of every nonzero of the validated
-// input (Container geometry already set) and returns both histograms;
+// keys forms the delta and value keys of every nonzero (Container geometry
+// already set; row_ptr validated on the host) and returns both histograms;
+// with inputs_on_device() the col / vals pointers are device pointers, and
+// keys also checks the columns (range, ascending within rows), returning the
+// error a serial scan of the rows would find first;
 // streams then maps every nonzero to its symbols and writes the words and
 // escape regions of every wave, with their offsets, into the container
 // (Sec. IV-B, IV-E, IV-F), exactly as the host passes would.
@@ -104,9 +107,11 @@ class DeviceEncoder {
     virtual std::string keys(const Container &c, const int32_t *col, const void *vals,
                              std::vector<KeyCount> &dhist, std::vector<KeyCount> &vhist) = 0;
     virtual std::string streams(const AlphabetMap &d, const AlphabetMap &v, Container &c) = 0;
+    virtual bool inputs_on_device() const = 0;
 };
-// A DeviceEncoder on the current GPU running on `stream` (a hipStream_t).
-DeviceEncoder *new_device_encoder(void *stream);
+// A DeviceEncoder on the current GPU running on `stream` (a hipStream_t);
+// device_inputs: col and vals handed to encode_csr are device pointers.
+DeviceEncoder *new_device_encoder(void *stream, bool device_inputs = false);
 
 // All functions return an empty string on success or an error message whose
 // first word is the error class ("EINVAL: ...", "ERANGE: ...", ...).

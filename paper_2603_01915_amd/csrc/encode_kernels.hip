@@ -198,11 +198,14 @@ __global__ __launch_bounds__(256) void enc_words_kernel(WordJobDev J) {
 // Delta key of every nonzero g (Sec. IV-A): the difference to the previous
 // column, except at the start of a row or of a lane stream, where it is the
 // column relative to first_base of the row holding g.  The row is found by a
-// binary search of row_ptr (the last i with row_ptr[i] <= g).
+// binary search of row_ptr (the last i with row_ptr[i] <= g).  Columns out of
+// [0, n) or below their predecessor in the row are reported in *bad as the
+// smallest 2 g + (1 for unsorted), the error a serial scan finds first.
 __global__ __launch_bounds__(256) void enc_keys_kernel(const int32_t *__restrict__ row_ptr, int64_t m,
-                                                       const int32_t *__restrict__ col, int64_t nnz,
+                                                       const int32_t *__restrict__ col, int64_t nnz, int64_t n,
                                                        int32_t layout, int32_t lane_nnz, uint32_t first_mode,
-                                                       uint32_t *__restrict__ dkey) {
+                                                       uint32_t *__restrict__ dkey,
+                                                       unsigned long long *__restrict__ bad) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nnz;
          g += (int64_t)gridDim.x * blockDim.x) {
         int64_t lo = 0, hi = m;  // row_ptr[lo] <= g < row_ptr[hi]
@@ -213,9 +216,12 @@ __global__ __launch_bounds__(256) void enc_keys_kernel(const int32_t *__restrict
         }
         const bool row_start = row_ptr[lo] == g;
         const bool lane_start = layout == (int32_t)kLayoutRow ? row_start : g % lane_nnz == 0;
-        const uint32_t c = (uint32_t)col[g];
+        const int32_t cg = col[g];
+        const uint32_t c = (uint32_t)cg;
         dkey[g] = (row_start || lane_start) ? c - first_base(first_mode, (uint32_t)lo)
                                             : c - (uint32_t)col[g - 1];
+        if (cg < 0 || cg >= n) atomicMin(bad, (unsigned long long)(2 * g));
+        else if (!row_start && cg < col[g - 1]) atomicMin(bad, (unsigned long long)(2 * g + 1));
     }
 }
 
@@ -391,24 +397,44 @@ std::string device_histogram(const K *keys, int64_t n, hipStream_t st, std::vect
 
 class GpuEncoder final : public DeviceEncoder {
   public:
-    explicit GpuEncoder(void *stream) : st_((hipStream_t)stream) {}
+    GpuEncoder(void *stream, bool device_inputs) : st_((hipStream_t)stream), dev_in_(device_inputs) {}
+
+    bool inputs_on_device() const override { return dev_in_; }
 
     std::string keys(const Container &c, const int32_t *col, const void *vals, std::vector<KeyCount> &dhist,
                      std::vector<KeyCount> &vhist) override {
         const int64_t nnz = c.nnz;
         f64_ = c.dtype == kF64;
         const size_t vb = f64_ ? 8 : 4;
+        unsigned long long *bad = nullptr;
         ENC_TRY(B_.alloc(rp_, c.row_ptr.size()));
-        ENC_TRY(B_.alloc(col_, nnz));
-        ENC_TRY(B_.alloc(vals_, nnz * vb));
         ENC_TRY(B_.alloc(dkey_, nnz));
+        ENC_TRY(B_.alloc(bad, 1));
+        if (dev_in_) {
+            col_ = (int32_t *)col;
+            vals_ = (uint8_t *)vals;
+        } else {
+            ENC_TRY(B_.alloc(col_, nnz));
+            ENC_TRY(B_.alloc(vals_, nnz * vb));
+        }
         ENC_TRY(hipMemcpyAsync(rp_, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st_));
+        ENC_TRY(hipMemsetAsync(bad, 0xff, 8, st_));
         if (nnz) {
-            ENC_TRY(hipMemcpyAsync(col_, col, nnz * 4, hipMemcpyHostToDevice, st_));
-            ENC_TRY(hipMemcpyAsync(vals_, vals, nnz * vb, hipMemcpyHostToDevice, st_));
-            hipLaunchKernelGGL(enc_keys_kernel, dim3(elem_grid(nnz)), dim3(256), 0, st_, rp_, c.m, col_, nnz,
-                               (int32_t)c.layout, (int32_t)c.lane_nnz, c.first_mode, dkey_);
+            if (!dev_in_) {
+                ENC_TRY(hipMemcpyAsync(col_, col, nnz * 4, hipMemcpyHostToDevice, st_));
+                ENC_TRY(hipMemcpyAsync(vals_, vals, nnz * vb, hipMemcpyHostToDevice, st_));
+            }
+            hipLaunchKernelGGL(enc_keys_kernel, dim3(elem_grid(nnz)), dim3(256), 0, st_, rp_, c.m, col_, nnz, c.n,
+                               (int32_t)c.layout, (int32_t)c.lane_nnz, c.first_mode, dkey_, bad);
             ENC_TRY(hipGetLastError());
+        }
+        unsigned long long hbad = 0;
+        ENC_TRY(hipMemcpyAsync(&hbad, bad, 8, hipMemcpyDeviceToHost, st_));
+        ENC_TRY(hipStreamSynchronize(st_));
+        if (hbad != ~0ull) {
+            const int64_t g = (int64_t)(hbad >> 1), row = row_of(c.row_ptr, g);
+            if (hbad & 1) return "EUNSORTED: columns not ascending in row " + std::to_string(row);
+            return "ERANGE: column index out of range in row " + std::to_string(row);
         }
         std::string e = device_histogram(dkey_, nnz, st_, dhist);
         if (!e.empty()) return e;
@@ -420,6 +446,7 @@ class GpuEncoder final : public DeviceEncoder {
 
   private:
     hipStream_t st_;
+    bool dev_in_;
     DevBuffers B_;
     bool f64_ = false;
     int32_t *rp_ = nullptr, *col_ = nullptr;
@@ -595,6 +622,6 @@ std::string GpuEncoder::streams(const AlphabetMap &da, const AlphabetMap &va, Co
 
 }  // namespace
 
-DeviceEncoder *new_device_encoder(void *stream) { return new GpuEncoder(stream); }
+DeviceEncoder *new_device_encoder(void *stream, bool device_inputs) { return new GpuEncoder(stream, device_inputs); }
 
 }  // namespace dtans

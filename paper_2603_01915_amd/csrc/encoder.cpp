@@ -407,7 +407,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
             if (i >= 0) return fail("EINVAL", "row_ptr decreases at row " + std::to_string(i));
         std::vector<int64_t> brow(T, -1);
         std::vector<int> bkind(T, 0);
-        parallel_chunks(m, T, [&](int64_t b, int64_t e, int t) {
+        // device inputs: the columns are checked on the device (keys)
+        if (!(dev && dev->inputs_on_device())) parallel_chunks(m, T, [&](int64_t b, int64_t e, int t) {
             for (int64_t i = b; i < e; ++i)
                 for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
                     const int kind = (col[q] < 0 || col[q] >= n) ? 1

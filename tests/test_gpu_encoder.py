@@ -139,3 +139,68 @@ def test_full_size_stencil_and_pruned(tmp_path):
              % (th, time.perf_counter() - t0))
     rp, ci, v = workloads.pruned_weight()
     both(tmp_path, "pruned", rp, ci, v, 4096)
+
+
+def device_arrays(torch, rp, ci, v):
+    return (torch.from_numpy(np.ascontiguousarray(rp, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ci, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(v)).cuda())
+
+
+@pytest.mark.parametrize("layout,T", LAYOUTS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_device_inputs_identical(tmp_path, layout, T, dtype):
+    """dtans_encode_csr_device (CSR arrays already in device memory) writes
+    the host encoder's container, including escape-heavy and empty rows."""
+    torch = need_gpu()
+    rng = np.random.default_rng(33)
+    m = 300
+    rows = [sorted(rng.choice(10 ** 6, size=rng.integers(0, 30), replace=False)) for _ in range(m)]
+    rows[5] = []
+    rows[6] = list(range(0, 3000, 2))
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    rp = rp.astype(np.int32)
+    ci = np.array([c for r in rows for c in r], np.int64).astype(np.int32)
+    v = rng.choice(rng.standard_normal(6000), size=len(ci)).astype(dtype)
+    progress("device inputs %s %d %s" % (layout, T, dtype.__name__))
+    A = P.Matrix.from_csr(rp, ci, v, 10 ** 6, layout=layout, lane_nnz=T)
+    B = P.Matrix.from_csr_device(*device_arrays(torch, rp, ci, v), 10 ** 6, layout=layout, lane_nnz=T)
+    pa, pb = str(tmp_path / "h.dtans"), str(tmp_path / "d.dtans")
+    A.save(pa)
+    B.save(pb)
+    assert open(pa, "rb").read() == open(pb, "rb").read()
+    r2, c2, v2 = oracle.decode(pb)
+    assert np.array_equal(r2, rp) and np.array_equal(c2, ci)
+    assert np.array_equal(np.asarray(v2).view(np.uint8), v.view(np.uint8))
+
+
+def test_device_inputs_errors():
+    """Bad columns in device arrays give the host encoder's error class and
+    the first failing row (a serial scan's first error), and no handle."""
+    torch = need_gpu()
+    from paper_2603_01915_amd import _lib
+
+    rp = np.array([0, 2, 4, 6, 8], np.int32)
+    good = np.array([1, 3, 0, 2, 5, 6, 1, 7], np.int32)
+    v = np.ones(8)
+    cases = [
+        (np.array([1, 3, 0, 2, 6, 5, 1, 9], np.int32), "EUNSORTED", 2),  # row 2 unsorted before row 3 range
+        (np.array([1, 3, 0, 8, 6, 5, 1, 7], np.int32), "ERANGE", 1),     # 8 >= n in row 1
+        (np.array([1, 3, -1, 2, 5, 6, 1, 7], np.int32), "ERANGE", 1),
+        (np.array([3, 1, 0, 2, 5, 6, 1, 7], np.int32), "EUNSORTED", 0),
+    ]
+    progress("device inputs: error rows")
+    for ci, cls, row in cases:
+        for host in (True, False):
+            with pytest.raises(_lib.DtansError) as ei:
+                if host:
+                    P.Matrix.from_csr(rp, ci, v, 8)
+                else:
+                    P.Matrix.from_csr_device(*device_arrays(torch, rp, ci, v), 8)
+            assert str(ei.value).find(cls) >= 0 and str(ei.value).endswith("row %d" % row), (str(ei.value), host)
+    B = P.Matrix.from_csr_device(*device_arrays(torch, rp, good, v), 8)
+    assert B.nnz == 8
+    with pytest.raises(_lib.DtansError):
+        P.Matrix.from_csr_device(*device_arrays(torch, rp, good, v), 8, layout="row", lane_nnz=0,
+                                 max_mult=300)
