@@ -147,7 +147,7 @@ struct Fit {
 // Choose which symbols get table slots and their multiplicities so that the
 // expected encoded size (coded bits + raw bits of escaped symbols) is
 // smallest over a search of the table size.
-Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta, int cap) {
+Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta, int cap, int threads) {
     std::vector<KeyCount> cand;
     int64_t forced_esc = 0;
     for (const auto &kc : hist) {
@@ -196,20 +196,29 @@ Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta,
     grid.push_back(tmax);
     std::sort(grid.begin(), grid.end());
     grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
+    // the sizes are evaluated in parallel, then scanned in order (the first
+    // strictly smaller size wins, as in a serial search)
+    auto evaluate_all = [&](const std::vector<int> &ts) {
+        std::vector<double> bits(ts.size());
+        parallel_chunks((int64_t)ts.size(), threads, [&](int64_t b, int64_t e, int) {
+            for (int64_t i = b; i < e; ++i) bits[i] = evaluate(ts[i], nullptr);
+        });
+        return bits;
+    };
+    const std::vector<double> gbits = evaluate_all(grid);
     double best_bits = INFINITY;
     size_t best_i = 0;
-    for (size_t i = 0; i < grid.size(); ++i) {
-        double b = evaluate(grid[i], nullptr);
-        if (b < best_bits) { best_bits = b; best_i = i; }
-    }
+    for (size_t i = 0; i < grid.size(); ++i)
+        if (gbits[i] < best_bits) { best_bits = gbits[i]; best_i = i; }
     int lo = best_i > 0 ? grid[best_i - 1] : grid[0];
     int hi = best_i + 1 < grid.size() ? grid[best_i + 1] : grid[best_i];
     int best_t = grid[best_i];
     int step = std::max(1, (hi - lo) / 64);
-    for (int t = lo; t <= hi; t += step) {
-        double b = evaluate(t, nullptr);
-        if (b < best_bits) { best_bits = b; best_t = t; }
-    }
+    std::vector<int> fine;
+    for (int t = lo; t <= hi; t += step) fine.push_back(t);
+    const std::vector<double> fbits = evaluate_all(fine);
+    for (size_t i = 0; i < fine.size(); ++i)
+        if (fbits[i] < best_bits) { best_bits = fbits[i]; best_t = fine[i]; }
     evaluate(best_t, &best);
     return best;
 }
@@ -479,8 +488,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
         dhist = histogram(dkey, threads);
         vhist = histogram(vkey, threads);
     }
-    Fit dfit = fit_alphabet(dhist, 32, true, (int)p.max_mult);
-    Fit vfit = fit_alphabet(vhist, dtype == kF64 ? 64 : 32, false, (int)p.max_mult);
+    Fit dfit = fit_alphabet(dhist, 32, true, (int)p.max_mult, threads);
+    Fit vfit = fit_alphabet(vhist, dtype == kF64 ? 64 : 32, false, (int)p.max_mult, threads);
     SlotMap dsm, vsm;
     build_table(dfit, p.seed, c.dtab, dsm);
     build_table(vfit, p.seed ^ 0xd1b54a32d192ed03ull, c.vtab, vsm);
