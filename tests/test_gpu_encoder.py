@@ -141,6 +141,20 @@ def test_full_size_stencil_and_pruned(tmp_path):
     both(tmp_path, "pruned", rp, ci, v, 4096)
 
 
+def test_full_size_rmat(tmp_path):
+    """R-MAT scale 22 (2^22 rows, 67 M nonzeros, tens of millions of escaped
+    deltas), from host and from device arrays."""
+    torch = need_gpu()
+    rp, ci, v = workloads.rmat(22)
+    n = 1 << 22
+    B = both(tmp_path, "rmat22", rp, ci, v, n)
+    assert B.info()["esc_delta"] > 10 ** 7
+    D = P.Matrix.from_csr_device(*device_arrays(torch, rp, ci, v), n)
+    pd = str(tmp_path / "rmat22_dev.dtans")
+    D.save(pd)
+    assert open(pd, "rb").read() == open(str(tmp_path / "rmat22_gpu.dtans"), "rb").read()
+
+
 def device_arrays(torch, rp, ci, v):
     return (torch.from_numpy(np.ascontiguousarray(rp, np.int32)).cuda(),
             torch.from_numpy(np.ascontiguousarray(ci, np.int32)).cuda(),
