@@ -202,6 +202,22 @@ dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t 
                           int64_t lddx, double alpha, double beta, void *stream);
 
 /*
+ * Symmetric product from one triangle (Sec. V: symmetric matrices multiplied
+ * through one half, off-diagonal entries not duplicated).  mat holds the
+ * strictly upper (or strictly lower) triangle S of a symmetric n x n matrix
+ * A = S + S^T + diag(d); diag holds d (n values of the matrix's dtype,
+ * device pointer; NULL for a zero diagonal).  Computes
+ * y = alpha * (S x + S^T x + d .* x) + beta * y on `stream`: the product on
+ * S (beta applied there), the diagonal term, then the transposed product on S
+ * adding into y, so the summation order of the S^T part is not deterministic.
+ * x and y are n-vectors in device memory and must not overlap.  DTANS_EINVAL
+ * for a non-square mat, null or aliased vectors; otherwise as dtans_spmv and
+ * dtans_spmm_t.  mat must not contain diagonal entries (they would count twice).
+ */
+dtans_status dtans_spmv_sym(dtans_matrix *mat, const void *diag, const void *x, void *y, double alpha,
+                            double beta, void *stream);
+
+/*
  * Decode the whole matrix back to CSR on the device (verification; the
  * result is bit-identical to the encoded CSR).  Device pointers: row_ptr
  * (m+1 int32), col_idx (nnz int32), vals (nnz values).

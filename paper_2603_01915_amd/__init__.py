@@ -99,6 +99,25 @@ def _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, 
     return o
 
 
+def symmetric_split(row_ptr, col, vals):
+    """The strictly upper triangle (CSR arrays) and the diagonal (duplicates
+    summed) of a square CSR matrix, for ``Matrix.spmv_sym``.  The lower
+    triangle is not read: the matrix is taken to be symmetric.  Host-side
+    preprocessing for the encoder."""
+    rp = _np(row_ptr, np.int64)
+    ci = _np(col, np.int64)
+    v = _np(vals)
+    m = len(rp) - 1
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(rp))
+    up = ci > rows
+    diag = np.zeros(m, dtype=v.dtype)
+    on = ci == rows
+    np.add.at(diag, rows[on], v[on])
+    rpu = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(rows[up], minlength=m), out=rpu[1:])
+    return rpu.astype(np.int32), ci[up].astype(np.int32), v[up], diag
+
+
 class Matrix:
     """A CSR matrix encoded in CSR-dtANS (host container + device copy)."""
 
@@ -221,6 +240,31 @@ class Matrix:
             raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
         _lib.check(self._L.dtans_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
                                       ctypes.c_void_p(_stream(stream))))
+        return y
+
+    def spmv_sym(self, x, diag=None, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """y = alpha * (S x + S^T x + diag .* x) + beta * y, where this matrix
+        holds the strict triangle S of a symmetric matrix (see
+        ``symmetric_split``) and diag its diagonal (device tensor or None)."""
+        torch = _torch()
+        m, n = self.shape
+        if m != n:
+            raise ValueError("the triangle of a symmetric matrix must be square")
+        _dev(x, self.torch_dtype, "x", 1)
+        if x.numel() != n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), n))
+        if diag is not None:
+            _dev(diag, self.torch_dtype, "diag", 1)
+            if diag.numel() != n:
+                raise ValueError("diag has %d entries, expected %d" % (diag.numel(), n))
+        if y is None:
+            y = torch.empty(m, dtype=self.torch_dtype, device=x.device)
+            beta = 0.0
+        _dev(y, self.torch_dtype, "y", 1)
+        if y.numel() != m:
+            raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
+        _lib.check(self._L.dtans_spmv_sym(self._h, None if diag is None else diag.data_ptr(), x.data_ptr(),
+                                          y.data_ptr(), alpha, beta, ctypes.c_void_p(_stream(stream))))
         return y
 
     def spmm(self, X, Y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdtans.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["encoder.cpp", "capi.cpp", "kernels.hip", "encode_kernels.hip"]
+SOURCES = ["encoder.cpp", "capi.cpp", "kernels.hip", "encode_kernels.hip", "sym_kernels.hip"]
 ARCH = "gfx950"
 
 

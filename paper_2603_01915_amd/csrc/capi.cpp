@@ -16,6 +16,12 @@
 
 using namespace dtans;
 
+namespace dtans {
+// sym_kernels.hip: y[i] += alpha * d[i] * x[i]
+hipError_t launch_diag_axpy(bool f64, const void *d, const void *x, void *y, int64_t n, double alpha,
+                            hipStream_t st);
+}  // namespace dtans
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -748,6 +754,25 @@ dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t 
                                  plan_launch(mat), mat->partial, 8 * mat->partial_cap, st);
     if (e != hipSuccess) return hip_err(e, "dtans_spmm_t launch");
     return DTANS_OK;
+}
+
+dtans_status dtans_spmv_sym(dtans_matrix *mat, const void *diag, const void *x, void *y, double alpha,
+                            double beta, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    dtans_status s = check_handle(mat, st);
+    if (s) return s;
+    const Container &c = mat->c;
+    if (c.m != c.n) return set_err(DTANS_EINVAL, "the triangle of a symmetric matrix must be square");
+    if (c.m > 0 && (!x || !y)) return set_err(DTANS_EINVAL, "null vector");
+    if (x == y && c.m > 0) return set_err(DTANS_EINVAL, "y must not alias x");
+    // y = alpha S x + beta y, then y += alpha d .* x, then y += alpha S^T x
+    s = dtans_spmv(mat, x, y, alpha, beta, stream);
+    if (s) return s;
+    if (diag) {
+        hipError_t e = launch_diag_axpy(c.dtype == kF64, diag, x, y, c.m, alpha, st);
+        if (e != hipSuccess) return hip_err(e, "dtans_spmv_sym diagonal launch");
+    }
+    return dtans_spmm_t(mat, 1, x, 1, y, 1, alpha, 1.0, stream);
 }
 
 dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_idx, void *vals,

@@ -411,3 +411,45 @@ def test_spmm_t_both_paths(layout, T, dtype):
             scale = 0.75 * oracle.absmv(At.indptr, At.indices, At.data, dY[:, c]) + \
                 0.5 * np.abs(dX0[:, c].astype(np.float64))
             assert rel_error(out[:, c], ref, scale) <= TOL[dtype], (n, c)
+
+
+@pytest.mark.parametrize("layout,T", [("row", 0), ("nnz", 16)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_symmetric_half_storage(layout, T, dtype):
+    """y = alpha (S + S^T + diag(d)) x + beta y from the strict upper triangle
+    S only, against the oracle's product with the whole symmetric matrix;
+    also without a diagonal.  Sizes span several waves with a ragged tail and
+    rows of S without entries; the 27-point stencil (symmetrised) covers a
+    regular case."""
+    torch = need_gpu()
+    rng = np.random.default_rng(77)
+    cases = []
+    n = 3000
+    B = sp.random(n, n, density=0.003, format="csr", random_state=rng)
+    A = (B + B.T + sp.diags(rng.standard_normal(n))).tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    cases.append(("random", A))
+    rp, ci, v = workloads.stencil27(20)
+    S0 = sp.csr_matrix((v, ci, rp), shape=(20 ** 3, 20 ** 3))
+    A2 = ((S0 + S0.T) * 0.5).tocsr()
+    A2.sort_indices()
+    cases.append(("stencil20", A2))
+    for name, A in cases:
+        rpa, cia, va = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(dtype)
+        rpu, ciu, vu, d = P.symmetric_split(rpa, cia, va)
+        progress("symmetric %s %s %s" % (name, layout, dtype.__name__))
+        M = P.Matrix.from_csr(rpu, ciu, vu, A.shape[0], layout=layout, lane_nnz=T)
+        x = workloads.vector(A.shape[0], 3, dtype)
+        y0 = workloads.vector(A.shape[0], 4, dtype)
+        xt, dt = torch.from_numpy(x).cuda(), torch.from_numpy(d).cuda()
+        for alpha, beta in ((1.0, 0.0), (-0.5, 0.75)):
+            yt = torch.from_numpy(y0.copy()).cuda()
+            M.spmv_sym(xt, dt, yt, alpha=alpha, beta=beta)
+            check_spmv(yt.cpu().numpy(), rpa, cia, va, x, y0, alpha, beta, dtype)
+        # without the diagonal
+        yt = M.spmv_sym(xt)
+        Aod = sp.csr_matrix((vu, ciu, rpu), shape=A.shape)
+        Aod = (Aod + Aod.T).tocsr()
+        Aod.sort_indices()
+        check_spmv(yt.cpu().numpy(), Aod.indptr, Aod.indices, Aod.data, x, np.zeros_like(x), 1.0, 0.0, dtype)

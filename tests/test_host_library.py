@@ -33,7 +33,7 @@ def test_header_symbols_exported():
     names = set(re.findall(
         r"^\s*(?:dtans_status|void|const char \*|int64_t|int32_t)\s*\*?\s*(dtans_\w+)\s*\(",
         text, re.M))
-    assert len(names) == 26
+    assert len(names) == 27
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for n in sorted(names):
         assert hasattr(lib, n), n
@@ -397,3 +397,23 @@ def test_transpose_csr_matches_scipy():
         assert np.array_equal(vt, T.data)
     with pytest.raises(ValueError):
         transpose_csr(np.array([0, 1], np.int32), np.array([4], np.int32), np.ones(1), 4)
+
+
+def test_symmetric_split():
+    """Strict upper triangle and diagonal (duplicates summed) of a symmetric
+    matrix, against scipy; S + S^T + diag gives the matrix back."""
+    rng = np.random.default_rng(8)
+    B = sp.random(90, 90, density=0.05, format="csr", random_state=rng)
+    A = (B + B.T + sp.diags(rng.standard_normal(90))).tocsr()
+    A.sort_indices()
+    rpu, ciu, vu, d = P.symmetric_split(A.indptr, A.indices, A.data)
+    U = sp.triu(A, k=1).tocsr()
+    U.sort_indices()
+    assert np.array_equal(rpu, U.indptr) and np.array_equal(ciu, U.indices) and np.array_equal(vu, U.data)
+    assert np.array_equal(d, A.diagonal())
+    S = sp.csr_matrix((vu, ciu, rpu), shape=(90, 90))
+    assert abs(S + S.T + sp.diags(d) - A).max() == 0
+    # duplicated diagonal entries are summed
+    rpu, ciu, vu, d = P.symmetric_split(np.array([0, 2, 3], np.int32), np.array([0, 0, 1], np.int32),
+                                        np.array([1.5, 2.0, 4.0]))
+    assert list(d) == [3.5, 4.0] and len(ciu) == 0 and list(rpu) == [0, 0, 0]
