@@ -21,7 +21,8 @@ persistent launch, against one CSR launch per matrix), autograd (forward
 SpMM and backward transposed product with batch 16 on the pruned weight) and
 encode (host arrays to container: the host encoder against the one whose
 stream base/digit passes and word interleave run on the GPU, on the stencil
-and the pruned weight).
+and the pruned weight) and sym (a symmetric 27-point stencil multiplied
+through its strict upper triangle and diagonal, against the whole matrix).
 
 Prints one JSON line (see the keys below).
 """
@@ -147,7 +148,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="stencil",
-                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch, autograd or encode")
+                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch, autograd, encode or sym")
     ap.add_argument("--layout", default="auto")
     ap.add_argument("--lane-nnz", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
@@ -193,6 +194,8 @@ def main():
         return bench_autograd(args, torch, P)
     if args.workload == "encode":
         return bench_encode(args, torch, P)
+    if args.workload == "sym":
+        return bench_sym(args, torch, P)
     log("generating workload %s" % args.workload)
     W = make_workload(args.workload)
     rp, ci, v, n, k = W["rp"], W["ci"], W["v"], W["n"], W["k"]
@@ -461,6 +464,72 @@ def bench_encode(args, torch, P):
            "host_threads": min(os.cpu_count() or 4, 32), "roofline": None,
            "note": "word-pass kernel times are in the rocprofv3 kernel trace; the rest of either call "
                    "(keys, alphabet fit, tables, symbol lookup, escapes) runs on the host"}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_sym(args, torch, P):
+    """A symmetric 128^3 27-point stencil in FP64 (the upper triangle of the
+    stencil mirrored, so the 216-value pool is kept): SpMV through the strict
+    upper triangle and the diagonal (dtans_spmv_sym, half storage) against the
+    ordinary SpMV on the whole encoded matrix; both rotate copies past the
+    MALL."""
+    import scipy.sparse as sp
+
+    import workloads
+
+    rp, ci, v = workloads.stencil27(128)
+    n = 128 ** 3
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    U = sp.triu(A, k=1).tocsr()
+    S = (sp.triu(A) + U.T).tocsr()
+    S.sort_indices()
+    rps, cis, vs = S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data
+    rpu, ciu, vu, d = P.symmetric_split(rps, cis, vs)
+    log("encoding the whole matrix (%d nonzeros) and its strict upper triangle (%d)" % (len(cis), len(ciu)))
+    F0 = P.Matrix.from_csr(rps, cis, vs, n)
+    H0 = P.Matrix.from_csr(rpu, ciu, vu, n)
+    fi, hi = F0.info(), H0.info()
+
+    def copies_of(M0, extra):
+        c = args.copies or max(1, math.ceil(2 * MALL_BYTES / (M0.info()["total_bytes"] + extra)))
+        mats = [M0]
+        if c > 1:
+            import tempfile
+
+            with tempfile.TemporaryDirectory() as td:
+                path = os.path.join(td, "a.dtans")
+                M0.save(path)
+                mats += [P.Matrix.load(path) for _ in range(c - 1)]
+        for M in mats:
+            M.to_device()
+        return mats
+
+    vec = 2 * n * 8
+    full, half = copies_of(F0, vec), copies_of(H0, vec + n * 8)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    nc = max(len(full), len(half))
+    xs = [torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1 for _ in range(nc)]
+    ys = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(nc)]
+    ds = [torch.from_numpy(d).cuda() for _ in range(len(half))]
+    fms, _ = time_steps(torch, lambda i: full[i % len(full)].spmv(xs[i % nc], ys[i % nc]), args.steps,
+                        args.warmup)
+    hms, _ = time_steps(torch, lambda i: half[i % len(half)].spmv_sym(xs[i % nc], ds[i % len(half)], ys[i % nc]),
+                        args.steps, args.warmup)
+    flops = 2.0 * len(cis)
+    res = {"metric": METRIC, "value": round(flops / (hms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hms, 6), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator)",
+           "config": {"workload": "symmetric stencil27 128^3 fp64 spmv through its strict upper triangle",
+                      "rows": n, "nnz_whole": len(cis), "nnz_triangle": len(ciu),
+                      "copies_rotated": [len(full), len(half)]},
+           "roofline": None,
+           "whole_matrix": {"ms": round(fms, 6), "GFLOP/s": round(flops / (fms * 1e-3) / 1e9, 3),
+                            "dtans_bytes": fi["total_bytes"], "bits_per_nnz": round(fi["bits_per_nnz"], 3)},
+           "half_storage": {"ms": round(hms, 6), "dtans_bytes": hi["total_bytes"] + n * 8,
+                            "bits_per_nnz_triangle": round(hi["bits_per_nnz"], 3),
+                            "transpose_path": "global atomics" if n * 8 > 64 * 1024 else "LDS copies"},
+           "note": "the transposed half scatters into y with atomic adds; GFLOP/s counts the whole matrix"}
     print(json.dumps(res), flush=True)
     return 0
 
