@@ -23,6 +23,9 @@ tests can run the same recipe at small sizes.
      index), CSR over rows.
   4b. batch: 64 square matrices with round(2^(10+6u)) rows, 8..64 columns per
      row within +-512 of the diagonal, a 64-value float pool per matrix.
+  5. graph models for the delta-entropy study: Erdős–Rényi G(n, d/(n-1)),
+     Watts–Strogatz (k neighbours, rewiring 0.1), Barabási–Albert (m links
+     per new node), as symmetric patterns.
 """
 from __future__ import annotations
 
@@ -217,3 +220,65 @@ def batch(count: int = 64, seed: int = 1005, lo_exp: int = 10, hi_exp: int = 16,
         vals = pool[rng.integers(0, 64, size=len(cols))]
         out.append((m, _to_csr(m, rows, cols, vals)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Random graph models for the delta-entropy study (Sec. IV-A, Fig. 4):
+# undirected simple graphs as symmetric CSR patterns (sorted columns, no
+# self loops), seeded.
+# ---------------------------------------------------------------------------
+def _sym_pattern(n: int, i: np.ndarray, j: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    a = np.concatenate([i, j]).astype(np.int64)
+    b = np.concatenate([j, i]).astype(np.int64)
+    keep = a != b
+    key = np.unique(a[keep] * n + b[keep])
+    r, c = key // n, key % n
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=rp[1:])
+    return rp.astype(np.int32), c.astype(np.int32)
+
+
+def erdos_renyi(n: int, avg_degree: float, seed: int = 3001):
+    """G(n, p) with p = avg_degree / (n - 1)."""
+    rng = np.random.default_rng(seed)
+    p = avg_degree / (n - 1)
+    I, J = [], []
+    for i in range(n - 1):
+        k = rng.binomial(n - 1 - i, p)
+        if k:
+            J.append(rng.choice(np.arange(i + 1, n), size=k, replace=False))
+            I.append(np.full(k, i))
+    if not I:
+        return _sym_pattern(n, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    return _sym_pattern(n, np.concatenate(I), np.concatenate(J))
+
+
+def watts_strogatz(n: int, k: int, beta: float = 0.1, seed: int = 3002):
+    """Ring lattice with k neighbours per node (k/2 on each side), each edge's
+    far end rewired to a uniform node with probability beta."""
+    rng = np.random.default_rng(seed)
+    I, J = [], []
+    for s in range(1, k // 2 + 1):
+        i = np.arange(n)
+        j = (i + s) % n
+        j = np.where(rng.random(n) < beta, rng.integers(0, n, n), j)
+        I.append(i)
+        J.append(j)
+    return _sym_pattern(n, np.concatenate(I), np.concatenate(J))
+
+
+def barabasi_albert(n: int, m: int, seed: int = 3003):
+    """Preferential attachment: every new node links to m earlier nodes drawn
+    with probability proportional to their degree (m initial nodes)."""
+    rng = np.random.default_rng(seed)
+    targets = list(range(m))
+    repeated: List[int] = []
+    I, J = [], []
+    for v in range(m, n):
+        for t in set(targets):
+            I.append(v)
+            J.append(t)
+        repeated.extend(targets)
+        repeated.extend([v] * m)
+        targets = [repeated[x] for x in rng.integers(0, len(repeated), m)]
+    return _sym_pattern(n, np.array(I, np.int64), np.array(J, np.int64))
