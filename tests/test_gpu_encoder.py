@@ -88,6 +88,28 @@ def test_escape_heavy(tmp_path, dtype):
             assert inf["esc_delta"] > 1000 and inf["esc_value"] > 1000
 
 
+def test_sort_rows_option(tmp_path):
+    """Rows given with unsorted columns and sort_rows: both encoders sort them
+    the same way (values follow their columns)."""
+    rng = np.random.default_rng(41)
+    rp, ci, v = rand_csr(500, 400, 0.03, 5)
+    perm_ci, perm_v = ci.copy(), v.copy()
+    for i in range(500):
+        b, e = rp[i], rp[i + 1]
+        p = rng.permutation(e - b)
+        perm_ci[b:e] = ci[b:e][p]
+        perm_v[b:e] = v[b:e][p]
+    need_gpu()
+    A = P.Matrix.from_csr(rp, perm_ci, perm_v, 400, sort_rows=True)
+    B = P.Matrix.from_csr(rp, perm_ci, perm_v, 400, sort_rows=True, gpu_encode=True)
+    pa, pb = str(tmp_path / "h.dtans"), str(tmp_path / "g.dtans")
+    A.save(pa)
+    B.save(pb)
+    assert open(pa, "rb").read() == open(pb, "rb").read()
+    r2, c2, v2 = oracle.decode(pb)
+    assert np.array_equal(c2, ci) and np.array_equal(np.asarray(v2), v)
+
+
 def test_long_rows_many_flag_words(tmp_path):
     """Rows of 1..1500 nonzeros side by side in one wave: lanes start their
     backward pass at very different steps and use up to 24 flag words."""
@@ -206,13 +228,13 @@ def test_device_inputs_errors():
     ]
     progress("device inputs: error rows")
     for ci, cls, row in cases:
-        for host in (True, False):
+        for path in ("host", "gpu", "device"):
             with pytest.raises(_lib.DtansError) as ei:
-                if host:
-                    P.Matrix.from_csr(rp, ci, v, 8)
-                else:
+                if path == "device":
                     P.Matrix.from_csr_device(*device_arrays(torch, rp, ci, v), 8)
-            assert str(ei.value).find(cls) >= 0 and str(ei.value).endswith("row %d" % row), (str(ei.value), host)
+                else:
+                    P.Matrix.from_csr(rp, ci, v, 8, gpu_encode=path == "gpu")
+            assert str(ei.value).find(cls) >= 0 and str(ei.value).endswith("row %d" % row), (str(ei.value), path)
     B = P.Matrix.from_csr_device(*device_arrays(torch, rp, good, v), 8)
     assert B.nnz == 8
     with pytest.raises(_lib.DtansError):
