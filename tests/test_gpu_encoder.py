@@ -134,6 +134,18 @@ def test_degenerate_sizes(tmp_path):
     both(tmp_path, "one", np.array([0, 1], np.int32), np.array([0], np.int32), np.ones(1), 1)
     rp, ci, v = rand_csr(65, 65, 0.3, 4)
     both(tmp_path, "wave_plus_one", rp, ci, v, 65, layout="row")
+    # the same from device arrays
+    torch = need_gpu()
+    cases = [(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), 5),
+             (np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0), 5),
+             (np.array([0, 1], np.int32), np.array([0], np.int32), np.ones(1), 1), (rp, ci, v, 65)]
+    for q, (r, c, x, n) in enumerate(cases):
+        A = P.Matrix.from_csr(r, c, x, n)
+        B = P.Matrix.from_csr_device(*device_arrays(torch, r, c, x), n)
+        pa, pb = str(tmp_path / ("dh%d" % q)), str(tmp_path / ("dd%d" % q))
+        A.save(pa)
+        B.save(pb)
+        assert open(pa, "rb").read() == open(pb, "rb").read(), q
 
 
 def test_all_bases_256(tmp_path):
