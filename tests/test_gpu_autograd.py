@@ -114,7 +114,8 @@ def test_linear_module(transposed_copy):
     from paper_2603_01915_amd.autograd import DtansLinear
 
     rp, ci, v = workloads.pruned_weight(rows=200, cols=128)
-    lin = DtansLinear.from_csr(rp, ci, v, 128, transposed_copy=transposed_copy)
+    # the transposed-copy case also encodes both matrices with the GPU passes
+    lin = DtansLinear.from_csr(rp, ci, v, 128, transposed_copy=transposed_copy, gpu_encode=transposed_copy)
     assert (lin.At is not None) == transposed_copy
     x = torch.randn(5, 128, device="cuda", requires_grad=True)
     y = lin(x)
