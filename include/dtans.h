@@ -17,10 +17,17 @@
  *   - "host" pointers point to CPU memory and are only read during the call
  *     (borrowed).  "device" pointers are HIP device allocations owned by the
  *     caller (e.g. torch tensor data_ptr()); the library never frees them.
- *   - Device calls are asynchronous on the caller's HIP stream (NULL = the
- *     null stream) and never synchronize implicitly.  Arguments are validated
- *     on the host before anything is launched; a launch failure returns
- *     DTANS_EHIP.
+ *   - Product calls (dtans_spmv, dtans_spmm, dtans_spmm_t, dtans_spmv_sym,
+ *     dtans_decode_csr, dtans_batch_spmv, dtans_csr_spmv, dtans_csr_spmm)
+ *     are asynchronous on the caller's HIP stream (NULL = the null stream),
+ *     allocate nothing and never synchronize.  They need the matrix on the
+ *     current device with scratch for their number of right-hand sides:
+ *     dtans_to_device uploads it and reserves for one right-hand side,
+ *     dtans_reserve for more; otherwise a product call returns DTANS_EINVAL
+ *     without launching.  Only dtans_to_device, dtans_reserve, the encoders,
+ *     dtans_batch_create, dtans_csr_create and dtans_autotune allocate device
+ *     memory or wait for the device.  Arguments are validated on the host
+ *     before anything is launched; a launch failure returns DTANS_EHIP.
  *   - Vectors have the matrix's value type (float for DTANS_F32, double for
  *     DTANS_F64); alpha/beta are passed as double and rounded to that type.
  *     beta == 0 means the output is not read (it may hold NaN).
@@ -163,9 +170,21 @@ dtans_status dtans_encode_csr_device(int64_t m, int64_t n, int64_t nnz, const in
 dtans_status dtans_save(const dtans_matrix *mat, const char *path);
 dtans_status dtans_load(const char *path, dtans_matrix **out);
 
-/* Copy the encoded matrix to the current HIP device (idempotent; the copy is
- * enqueued on `stream`).  The device multiplication calls upload implicitly. */
+/* Copy the encoded matrix to the current HIP device and reserve the scratch
+ * of products with one right-hand side (idempotent).  The copies are
+ * enqueued on `stream` and the call waits for them, so that products on any
+ * stream of this device find the matrix in place.  DTANS_EINVAL when the
+ * matrix already lives on another device. */
 dtans_status dtans_to_device(dtans_matrix *mat, void *stream);
+
+/* Upload the matrix if needed (as dtans_to_device) and grow its device
+ * scratch so that dtans_spmm and dtans_spmm_t with up to k right-hand sides
+ * need no allocation (the nonzero-balanced layout keeps two partial sums per
+ * lane and column of a pass of at most 32 columns; the transposed product
+ * keeps per-CU copies of a block of dX).  Growing waits for the device
+ * before the smaller buffer is freed.  k >= 1; DTANS_ENOMEM / DTANS_EHIP on
+ * allocation failure. */
+dtans_status dtans_reserve(dtans_matrix *mat, int32_t k, void *stream);
 
 /* Sizes, entropies and launch configuration. */
 dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *out);

@@ -124,6 +124,7 @@ class Matrix:
     def __init__(self, handle: int):
         self._h = ctypes.c_void_p(handle)
         self._L = _lib.load()
+        self._reserved = 0  # right-hand sides the device scratch is sized for
         inf = self.info()
         self.shape = (inf["m"], inf["n"])
         self.nnz = inf["nnz"]
@@ -221,8 +222,23 @@ class Matrix:
         _lib.check(self._L.dtans_set_launch(self._h, waves_per_wg, wg_per_cu, stream_stage))
 
     def to_device(self, stream=None) -> "Matrix":
+        """Upload to the current device (waits for the copies) and reserve the
+        scratch of one right-hand side."""
         _lib.check(self._L.dtans_to_device(self._h, ctypes.c_void_p(_stream(stream))))
+        self._reserved = max(self._reserved, 1)
         return self
+
+    def reserve(self, k: int, stream=None) -> "Matrix":
+        """Upload if needed and size the device scratch for products with up to
+        k right-hand sides (the C product calls themselves never allocate)."""
+        _lib.check(self._L.dtans_reserve(self._h, int(k), ctypes.c_void_p(_stream(stream))))
+        self._reserved = max(self._reserved, int(k))
+        return self
+
+    def _ready(self, k: int, stream) -> None:
+        # the binding's convenience: upload / grow the scratch on first use
+        if k > self._reserved:
+            self.reserve(k, stream)
 
     # ---------------------------------------------------------- multiplies
     def spmv(self, x, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
@@ -238,6 +254,7 @@ class Matrix:
         _dev(y, self.torch_dtype, "y", 1)
         if y.numel() != m:
             raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
+        self._ready(1, stream)
         _lib.check(self._L.dtans_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
                                       ctypes.c_void_p(_stream(stream))))
         return y
@@ -263,6 +280,7 @@ class Matrix:
         _dev(y, self.torch_dtype, "y", 1)
         if y.numel() != m:
             raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
+        self._ready(1, stream)
         _lib.check(self._L.dtans_spmv_sym(self._h, None if diag is None else diag.data_ptr(), x.data_ptr(),
                                           y.data_ptr(), alpha, beta, ctypes.c_void_p(_stream(stream))))
         return y
@@ -283,6 +301,7 @@ class Matrix:
             raise ValueError("Y must be [%d, %d]" % (m, k))
         if k == 0:
             return Y
+        self._ready(k, stream)
         _lib.check(self._L.dtans_spmm(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
                                       alpha, beta, ctypes.c_void_p(_stream(stream))))
         return Y
@@ -303,6 +322,7 @@ class Matrix:
             raise ValueError("dX must be [%d, %d]" % (n, k))
         if k == 0:
             return dX
+        self._ready(1, stream)
         _lib.check(self._L.dtans_spmm_t(self._h, k, dY.data_ptr(), _ld(dY), dX.data_ptr(),
                                         _ld(dX), alpha, beta, ctypes.c_void_p(_stream(stream))))
         return dX
@@ -315,6 +335,7 @@ class Matrix:
         rp = torch.empty(m + 1, dtype=torch.int32, device=dev)
         ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
         v = torch.empty(max(self.nnz, 1), dtype=self.torch_dtype, device=dev)
+        self._ready(1, stream)
         _lib.check(self._L.dtans_decode_csr(self._h, rp.data_ptr(), ci.data_ptr(), v.data_ptr(),
                                             ctypes.c_void_p(_stream(stream))))
         return rp, ci[:self.nnz], v[:self.nnz]
@@ -343,11 +364,16 @@ class CsrBaseline:
     def spmv(self, x, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
         torch = _torch()
         dt = torch.float64 if self.is_f64 else torch.float32
+        m, n = self.shape
         _dev(x, dt, "x", 1)
+        if x.numel() != n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), n))
         if y is None:
-            y = torch.empty(self.shape[0], dtype=dt, device=x.device)
+            y = torch.empty(m, dtype=dt, device=x.device)
             beta = 0.0
         _dev(y, dt, "y", 1)
+        if y.numel() != m:
+            raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
         _lib.check(self._L.dtans_csr_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
                                           ctypes.c_void_p(_stream(stream))))
         return y
@@ -355,12 +381,19 @@ class CsrBaseline:
     def spmm(self, X, Y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
         torch = _torch()
         dt = torch.float64 if self.is_f64 else torch.float32
+        m, n = self.shape
         _dev(X, dt, "X", 2)
+        if X.size(0) != n:
+            raise ValueError("X has %d rows, expected %d" % (X.size(0), n))
         k = X.size(1)
         if Y is None:
-            Y = torch.empty((self.shape[0], k), dtype=dt, device=X.device)
+            Y = torch.empty((m, k), dtype=dt, device=X.device)
             beta = 0.0
         _dev(Y, dt, "Y", 2)
+        if tuple(Y.shape) != (m, k):
+            raise ValueError("Y must be [%d, %d]" % (m, k))
+        if k == 0:
+            return Y
         _lib.check(self._L.dtans_csr_spmm(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
                                           alpha, beta, ctypes.c_void_p(_stream(stream))))
         return Y

@@ -72,6 +72,7 @@ SIGNATURES = {
     "dtans_save": (_I32, [_P, _S]),
     "dtans_load": (_I32, [_S, _PP]),
     "dtans_to_device": (_I32, [_P, _P]),
+    "dtans_reserve": (_I32, [_P, _I32, _P]),
     "dtans_matrix_info": (_I32, [_P, ctypes.POINTER(Info)]),
     "dtans_set_launch": (_I32, [_P, _I32, _I32, _I32]),
     "dtans_spmv": (_I32, [_P, _P, _P, _D, _D, _P]),

@@ -96,8 +96,12 @@ struct dtans_matrix {
     int device = -1, num_cus = 256;
     int waves_per_wg = 0, wg_per_cu = 0, stage = 0;
     DevMat view{};
-    double *partial = nullptr;
-    size_t partial_cap = 0;  // doubles
+    std::vector<uint32_t> escv32;  // FP32 escaped values as uploaded (kept with the handle)
+    // device scratch of the products (layout NNZ partial sums, the transposed
+    // product's per-CU copies of dX); sized by dtans_to_device / dtans_reserve
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int32_t reserved_k = 0;
 };
 
 struct dtans_batch {
@@ -116,8 +120,7 @@ struct dtans_csr {
     DevBufs bufs;
     CsrDev dev{};
     int device = -1, num_cus = 256;
-    double *partial = nullptr;
-    size_t partial_cap = 0;
+    double *partial = nullptr;  // variant 2: partial sums (owned by bufs)
     int64_t bytes = 0;
 };
 
@@ -231,12 +234,11 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     const bool f64 = c.dtype == kF64;
     const void *escv_src = c.escv.data();
     size_t escv_bytes = c.escv.size() * 8;
-    std::vector<uint32_t> escv32;
     if (!f64) {
-        escv32.resize(c.escv.size());
-        for (size_t i = 0; i < c.escv.size(); ++i) escv32[i] = (uint32_t)c.escv[i];
-        escv_src = escv32.data();
-        escv_bytes = escv32.size() * 4;
+        h->escv32.resize(c.escv.size());
+        for (size_t i = 0; i < c.escv.size(); ++i) h->escv32[i] = (uint32_t)c.escv[i];
+        escv_src = h->escv32.data();
+        escv_bytes = h->escv32.size() * 4;
     }
     void *p[16];
     HIP_TRY(h->bufs.upload(&p[0], h->gtab.data(), 8 * h->gtab.size(), st));
@@ -255,7 +257,8 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     HIP_TRY(h->bufs.upload(&p[13], h->nzr.data(), 4 * h->nzr.size(), st));
     HIP_TRY(h->bufs.upload(&p[14], h->empty_rows.data(), 4 * h->empty_rows.size(), st));
     HIP_TRY(h->bufs.upload(&p[15], h->split_long.data(), 4 * h->split_long.size(), st));
-    // the host staging vectors above must outlive the copies
+    // the copies complete before the call returns, so that products on any
+    // stream find the matrix in place (the one synchronisation of a handle)
     HIP_TRY(hipStreamSynchronize(st));
     DevMat &v = h->view;
     v.tab = (const uint64_t *)p[0];
@@ -294,23 +297,52 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     return DTANS_OK;
 }
 
-dtans_status ensure_partial(double *&buf, size_t &cap, size_t need) {
-    if (need <= cap) return DTANS_OK;
-    if (buf) {
-        hipError_t e = hipDeviceSynchronize();  // earlier launches may still use it
-        if (e != hipSuccess) return hip_err(e, "hipDeviceSynchronize");
-        (void)hipFree(buf);
-        buf = nullptr;
-        cap = 0;
+// scratch a product with up to k right-hand sides needs (either direction)
+size_t scratch_need(const dtans_matrix *h, int32_t k) {
+    const bool f64 = h->c.dtype == kF64;
+    const size_t a = spmm_scratch_bytes(h->view, k);
+    const size_t b = h->c.nnz > 0 ? spmm_t_work_bytes(h->view, f64, h->num_cus) : 0;
+    return std::max(a, b);
+}
+
+// Upload if needed, then grow the scratch to what products with up to k
+// right-hand sides need.  Growing waits for the device (earlier launches on
+// any stream may still read the old buffer) before the old one is freed.
+dtans_status reserve(dtans_matrix *h, int32_t k, hipStream_t st) {
+    dtans_status s = upload(h, st);
+    if (s) return s;
+    if (k <= h->reserved_k) return DTANS_OK;
+    const size_t need = scratch_need(h, k);
+    if (need > h->scratch_bytes) {
+        if (h->scratch) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(h->scratch));
+            h->scratch = nullptr;
+            h->scratch_bytes = 0;
+        }
+        HIP_TRY(hipMalloc(&h->scratch, need));
+        h->scratch_bytes = need;
     }
-    HIP_TRY(hipMalloc((void **)&buf, need * sizeof(double)));
-    cap = need;
+    h->reserved_k = std::max(h->reserved_k, std::min(k, kMaxPassCols));
+    if (k > kMaxPassCols) h->reserved_k = k;  // wider products reuse the pass-wide scratch
     return DTANS_OK;
 }
 
-dtans_status check_handle(dtans_matrix *h, hipStream_t st) {
+// Product calls allocate and synchronise nothing: the matrix must be on the
+// current device (dtans_to_device) with scratch for k columns (dtans_reserve;
+// dtans_to_device reserves for k = 1).
+dtans_status ready(dtans_matrix *h, int32_t k) {
     if (!h) return set_err(DTANS_EINVAL, "null matrix handle");
-    return upload(h, st);
+    if (!h->uploaded) return set_err(DTANS_EINVAL, "matrix is not on the device: call dtans_to_device first");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device)
+        return set_err(DTANS_EINVAL, "matrix was uploaded to device " + std::to_string(h->device) +
+                                         ", current device is " + std::to_string(dev));
+    if (k > 0 && scratch_need(h, k) > h->scratch_bytes)
+        return set_err(DTANS_EINVAL, "scratch reserved for fewer right-hand sides: call dtans_reserve(" +
+                                         std::to_string(k) + ") first");
+    return DTANS_OK;
 }
 
 int64_t sell_bytes(const Container &c, int slice) {
@@ -639,7 +671,14 @@ dtans_status dtans_load(const char *path, dtans_matrix **out) {
 }
 
 dtans_status dtans_to_device(dtans_matrix *mat, void *stream) {
-    return check_handle(mat, (hipStream_t)stream);
+    if (!mat) return set_err(DTANS_EINVAL, "null matrix handle");
+    return reserve(mat, 1, (hipStream_t)stream);
+}
+
+dtans_status dtans_reserve(dtans_matrix *mat, int32_t k, void *stream) {
+    if (!mat) return set_err(DTANS_EINVAL, "null matrix handle");
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    return reserve(mat, k, (hipStream_t)stream);
 }
 
 dtans_status dtans_set_launch(dtans_matrix *mat, int32_t waves_per_wg, int32_t wg_per_cu,
@@ -712,19 +751,15 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
 dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
                         int64_t ldy, double alpha, double beta, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    dtans_status s = check_handle(mat, st);
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    dtans_status s = ready(mat, k);
     if (s) return s;
     const Container &c = mat->c;
-    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
     if (ldx < k || ldy < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
     if (ldx >= (1ll << 31) || ldy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
     if ((c.m > 0 && !Y) || (c.n > 0 && c.nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
-    if (c.layout == kLayoutNnz) {
-        s = ensure_partial(mat->partial, mat->partial_cap, (size_t)(2 * c.num_lanes * std::min(k, 32)) + 1);
-        if (s) return s;
-    }
     hipError_t e = launch_spmm(mat->view, c.dtype == kF64, k, X, ldx, Y, ldy, alpha, beta,
-                               mat->partial, plan_launch(mat), st);
+                               (double *)mat->scratch, plan_launch(mat), st);
     if (e != hipSuccess) return hip_err(e, "dtans_spmm launch");
     return DTANS_OK;
 }
@@ -737,21 +772,16 @@ dtans_status dtans_spmv(dtans_matrix *mat, const void *x, void *y, double alpha,
 dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t lddy, void *dX,
                           int64_t lddx, double alpha, double beta, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    dtans_status s = check_handle(mat, st);
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    // the per-CU blocks of dX live in the handle's scratch (see launch_spmm_t)
+    dtans_status s = ready(mat, 1);
     if (s) return s;
     const Container &c = mat->c;
-    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
     if (lddy < k || lddx < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
     if (lddx >= (1ll << 31) || lddy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
     if ((c.n > 0 && !dX) || (c.m > 0 && c.nnz > 0 && !dY)) return set_err(DTANS_EINVAL, "null vector");
-    // the per-CU blocks of dX live in the handle's scratch (see launch_spmm_t)
-    const size_t wb = spmm_t_work_bytes(mat->view, c.dtype == kF64, mat->num_cus);
-    if (wb > 0 && c.nnz > 0) {
-        s = ensure_partial(mat->partial, mat->partial_cap, wb / 8 + 1);
-        if (s) return s;
-    }
     hipError_t e = launch_spmm_t(mat->view, c.dtype == kF64, k, dY, lddy, dX, lddx, alpha, beta,
-                                 plan_launch(mat), mat->partial, 8 * mat->partial_cap, st);
+                                 plan_launch(mat), mat->scratch, mat->scratch_bytes, st);
     if (e != hipSuccess) return hip_err(e, "dtans_spmm_t launch");
     return DTANS_OK;
 }
@@ -759,7 +789,7 @@ dtans_status dtans_spmm_t(dtans_matrix *mat, int32_t k, const void *dY, int64_t 
 dtans_status dtans_spmv_sym(dtans_matrix *mat, const void *diag, const void *x, void *y, double alpha,
                             double beta, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    dtans_status s = check_handle(mat, st);
+    dtans_status s = ready(mat, 1);
     if (s) return s;
     const Container &c = mat->c;
     if (c.m != c.n) return set_err(DTANS_EINVAL, "the triangle of a symmetric matrix must be square");
@@ -778,7 +808,7 @@ dtans_status dtans_spmv_sym(dtans_matrix *mat, const void *diag, const void *x, 
 dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_idx, void *vals,
                               void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    dtans_status s = check_handle(mat, st);
+    dtans_status s = ready(mat, 0);
     if (s) return s;
     const Container &c = mat->c;
     if (!row_ptr || (c.nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null output");
@@ -791,7 +821,7 @@ dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_
 
 void dtans_destroy(dtans_matrix *mat) {
     if (!mat) return;
-    if (mat->partial) (void)hipFree(mat->partial);
+    if (mat->scratch) (void)hipFree(mat->scratch);
     delete mat;
 }
 
@@ -808,7 +838,7 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must use the ROW layout");
         if (mats[i]->c.n * (int64_t)mats[i]->c.value_bytes() > (1ll << 32))
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must have x of at most 4 GiB");
-        dtans_status s = upload(mats[i], nullptr);
+        dtans_status s = reserve(mats[i], 1, nullptr);
         if (s) return s;
         if (mats[i]->device != mats[0]->device) return set_err(DTANS_EINVAL, "batch matrices on different devices");
     }
@@ -976,6 +1006,9 @@ dtans_status dtans_csr_create(int64_t m, int64_t n, int64_t nnz, const int32_t *
         (e = h->bufs.upload(&p[5], split_first.data(), 4 * split_first.size(), st)) != hipSuccess ||
         (e = h->bufs.upload(&p[6], split_last.data(), 4 * split_last.size(), st)) != hipSuccess ||
         (e = h->bufs.upload(&p[8], split_long.data(), 4 * split_long.size(), st)) != hipSuccess ||
+        (variant == 2 && (e = h->bufs.upload((void **)&h->partial, nullptr,
+                                             sizeof(double) * (size_t)(2 * c.num_lanes * kMaxPassCols + 1),
+                                             st)) != hipSuccess) ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         delete h;
         return hip_err(e, "dtans_csr_create upload");
@@ -1006,10 +1039,6 @@ dtans_status dtans_csr_spmm(dtans_csr *h, int32_t k, const void *X, int64_t ldx,
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != h->device) return set_err(DTANS_EINVAL, "CSR handle lives on another device");
-    if (h->dev.variant == 2) {
-        dtans_status s = ensure_partial(h->partial, h->partial_cap, (size_t)(2 * h->dev.num_lanes * std::min(k, 32)) + 1);
-        if (s) return s;
-    }
     hipError_t e = launch_csr(h->dev, h->f64, k, X, ldx, Y, ldy, alpha, beta, h->partial, h->num_cus,
                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_err(e, "dtans_csr_spmm launch");
@@ -1024,8 +1053,6 @@ dtans_status dtans_csr_spmv(dtans_csr *h, const void *x, void *y, double alpha, 
 int64_t dtans_csr_bytes(const dtans_csr *h) { return h ? h->bytes : 0; }
 
 void dtans_csr_destroy(dtans_csr *h) {
-    if (!h) return;
-    if (h->partial) (void)hipFree(h->partial);
     delete h;
 }
 
@@ -1132,7 +1159,7 @@ dtans_status dtans_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *ro
         }
         s = dtans_encode_csr(m, n, nnz, row_ptr, col_idx, vals, dtype, &eo, &r.h);
         if (s) return s;
-        s = dtans_to_device(r.h, r.st);
+        s = dtans_reserve(r.h, k, r.st);
         if (s) return s;
         size_t j = i;
         for (; j < cands.size() && cands[j].layout == cands[i].layout &&

@@ -189,36 +189,23 @@ Fit fit_alphabet(const std::vector<KeyCount> &hist, int raw_bits, bool is_delta,
         }
         return bits;
     };
-    // coarse grid over the table size, then every size around the best one
-    std::vector<int> grid;
-    for (int t = 1; t <= std::min(tmax, 64); ++t) grid.push_back(t);
-    for (double t = 64; t < tmax; t *= 1.08) grid.push_back((int)t);
-    grid.push_back(tmax);
-    std::sort(grid.begin(), grid.end());
-    grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
-    // the sizes are evaluated in parallel, then scanned in order (the first
-    // strictly smaller size wins, as in a serial search)
-    auto evaluate_all = [&](const std::vector<int> &ts) {
-        std::vector<double> bits(ts.size());
-        parallel_chunks((int64_t)ts.size(), threads, [&](int64_t b, int64_t e, int) {
-            for (int64_t i = b; i < e; ++i) bits[i] = evaluate(ts[i], nullptr);
-        });
-        return bits;
-    };
-    const std::vector<double> gbits = evaluate_all(grid);
+    // Every table size is evaluated (the size is not unimodal in t, so a
+    // coarse search can miss the optimum; for a fixed t the t most frequent
+    // admissible keys are an optimal choice, since an escaped symbol costs
+    // more than its raw bits >= 32 while a table slot costs at most
+    // log2(K) = 12 bits).  The sizes are evaluated in parallel, then scanned
+    // in order: the first strictly smaller size wins.
+    std::vector<double> bits(tmax);
+    // sizes dealt round-robin: an evaluation costs more for small t
+    const int nth = std::max(1, std::min(threads, tmax));
+    parallel_chunks((int64_t)nth, nth, [&](int64_t b, int64_t e, int) {
+        for (int64_t w = b; w < e; ++w)
+            for (int t = (int)w + 1; t <= tmax; t += nth) bits[t - 1] = evaluate(t, nullptr);
+    });
     double best_bits = INFINITY;
-    size_t best_i = 0;
-    for (size_t i = 0; i < grid.size(); ++i)
-        if (gbits[i] < best_bits) { best_bits = gbits[i]; best_i = i; }
-    int lo = best_i > 0 ? grid[best_i - 1] : grid[0];
-    int hi = best_i + 1 < grid.size() ? grid[best_i + 1] : grid[best_i];
-    int best_t = grid[best_i];
-    int step = std::max(1, (hi - lo) / 64);
-    std::vector<int> fine;
-    for (int t = lo; t <= hi; t += step) fine.push_back(t);
-    const std::vector<double> fbits = evaluate_all(fine);
-    for (size_t i = 0; i < fine.size(); ++i)
-        if (fbits[i] < best_bits) { best_bits = fbits[i]; best_t = fine[i]; }
+    int best_t = 1;
+    for (int t = 1; t <= tmax; ++t)
+        if (bits[t - 1] < best_bits) { best_bits = bits[t - 1]; best_t = t; }
     evaluate(best_t, &best);
     return best;
 }

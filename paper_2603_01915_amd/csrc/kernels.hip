@@ -1313,7 +1313,7 @@ template <typename F>
 hipError_t for_kc(int k, int kcmax, F f);
 template <typename F>
 hipError_t for_kc(int k, F f) {
-    return for_kc(k, 32, f);
+    return for_kc(k, kMaxPassCols, f);
 }
 template <typename F>
 hipError_t for_kc(int k, int kcmax, F f) {
@@ -1644,6 +1644,11 @@ hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t 
                                  partial, L, st);
     return spmm_impl<float>(a, k, (const float *)X, ldx, (float *)Y, ldy, alpha, beta, partial, L,
                             st);
+}
+
+size_t spmm_scratch_bytes(const DevMat &a, int k) {
+    if (a.layout != 2 || a.nnz == 0) return 0;
+    return (size_t)(2 * a.num_lanes * (int64_t)std::min(k, kMaxPassCols) + 1) * sizeof(double);
 }
 
 size_t spmm_t_work_bytes(const DevMat &a, bool f64, int num_cus) {

@@ -46,8 +46,14 @@ struct Launch {
     int wg_per_cu = 0;  // ring kernels: resident workgroups per CU (0: as many as fit)
 };
 
-// y = alpha*A*x + beta*y; k columns of X/Y (k = 1: SpMV); partial: layout NNZ
-// scratch of 2 * num_lanes * k doubles.
+// Columns of X/Y one SpMM launch takes at most (wider products run in
+// column passes that reuse the same scratch, in stream order).
+constexpr int kMaxPassCols = 32;
+// Device scratch launch_spmm needs for k columns: layout NNZ keeps a head and
+// a tail partial sum (double) per lane and column of a pass; 0 for layout ROW.
+size_t spmm_scratch_bytes(const DevMat &a, int k);
+// y = alpha*A*x + beta*y; k columns of X/Y (k = 1: SpMV); partial: device
+// scratch of at least spmm_scratch_bytes(a, k) bytes.
 hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, double alpha, double beta, double *partial, Launch L,
                        hipStream_t st);
