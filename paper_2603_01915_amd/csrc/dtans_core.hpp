@@ -125,6 +125,33 @@ DTANS_HD void group4_direct(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, 
     R = (m0 & 0xffu) * b1 * b23;
 }
 
+#if defined(__HIPCC__) || defined(__HIP__)
+// group4_direct from the high words of the four symbols' table entries
+// (delta symbols 1 and 3 hold base | digit << 8 in bits 0..15, value symbols
+// 2 and 4 in bits 16..31), on packed 16-bit lanes: v_perm gathers the bytes
+// into (u16, u16) pairs, one packed multiply-add forms both two-digit parts
+// and one packed multiply both two-base products, and a dot product joins
+// them.  Same D and R as group4_direct (all intermediate values < 2^16).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void group4_packed(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t h3,
+                                              uint32_t &D, uint32_t &R) {
+    const uint32_t P = __builtin_amdgcn_perm(h3, h1, 0x0c060c02u);  // (b1, b3)
+    const uint32_t Q = __builtin_amdgcn_perm(h2, h0, 0x0c050c01u);  // (d0, d2)
+    const uint32_t S = __builtin_amdgcn_perm(h3, h1, 0x0c070c03u);  // (d1, d3)
+    const uint32_t B = __builtin_amdgcn_perm(h2, h0, 0x0c040c00u);  // (b0, b2)
+    const u16x2 T = __builtin_bit_cast(u16x2, Q) * __builtin_bit_cast(u16x2, P) +
+                    __builtin_bit_cast(u16x2, S);                     // (d0 b1 + d1, d2 b3 + d3)
+    const u16x2 U = __builtin_bit_cast(u16x2, B) * __builtin_bit_cast(u16x2, P);  // (b0 b1, b2 b3)
+    const uint32_t V = __builtin_amdgcn_perm(1u, __builtin_bit_cast(uint32_t, U), 0x0c040302u);  // (b2 b3, 1)
+    D = __builtin_amdgcn_udot2(T, __builtin_bit_cast(u16x2, V), 0u, false);
+    R = __umul24((uint32_t)U.x, (uint32_t)U.y);
+    // R < 2^32 is used as a 32-bit factor of the 64-bit state products; the
+    // empty asm keeps the compiler from widening it to a 48-bit product
+    // (which would double the 64-bit multiplies of append_direct)
+    asm("" : "+v"(R));
+}
+#endif
+
 DTANS_HD bool append_direct(uint32_t &d, uint32_t &r, uint32_t D, uint32_t R, uint32_t &word) {
     const uint64_t r64 = (uint64_t)r * R;
     const uint64_t d64 = (uint64_t)d * R + D;

@@ -681,12 +681,13 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         if (m3) {
             uint32_t D, R;
             auto group = [&](int q, uint32_t &x) {
-                const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
-                const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
                 if constexpr (TF >= 1) {
-                    group4_direct(m0, m1, m2, m3, D, R);
+                    group4_packed((uint32_t)(e[q] >> 32), (uint32_t)(e[q + 1] >> 32),
+                                  (uint32_t)(e[q + 2] >> 32), (uint32_t)(e[q + 3] >> 32), D, R);
                     return append_direct(d, r, D, R, x);
                 } else {
+                    const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
+                    const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
                     group4(m0, m1, m2, m3, D, R);
                     return append_and_check(d, r, D, R, x);
                 }

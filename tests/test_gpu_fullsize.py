@@ -91,17 +91,72 @@ def test_pruned_full(pruned):
         progress("pruned spmm k=%d" % k)
         X = workloads.vector(n, 4, np.float32, k=k)
         Y = A.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
-        Yref = oracle.spmm(rp, ci, v, X)
-        for c in range(0, k, 7):
-            scale = oracle.absmv(rp, ci, v, X[:, c])
-            assert rel_error(Y[:, c], Yref[:, c], scale) <= TOL[np.float32]
+        check_all_columns(Y, rp, ci, v, X)
     progress("pruned spmm_t k=16")
     dY = workloads.vector(m, 5, np.float32, k=16)
     dX = A.spmm_t(torch.from_numpy(dY).cuda()).cpu().numpy()
     import scipy.sparse as sp
     At = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(m, n)).T.tocsr()
     At.sort_indices()
-    for c in range(0, 16, 5):
-        ref = oracle.spmtv(rp, ci, v, n, dY[:, c])
-        scale = oracle.absmv(At.indptr, At.indices, At.data, dY[:, c])
-        assert rel_error(dX[:, c], ref, scale) <= TOL[np.float32]
+    check_all_columns(dX, At.indptr.astype(np.int32), At.indices.astype(np.int32), At.data, dY)
+
+
+def check_all_columns(Y, rp, ci, v, X, Y0=None, alpha=1.0, beta=0.0, dtype=np.float32):
+    """Every column of Y against the oracle's FP64 product, relative to
+    (|A||X|) column by column (plus |beta Y0| when beta is not zero)."""
+    Yref = oracle.spmm(rp, ci, v, X, Y0, alpha=alpha, beta=beta)
+    scale = abs(alpha) * oracle.spmm(rp, ci, np.abs(np.asarray(v, np.float64)), np.abs(np.asarray(X, np.float64)))
+    if beta != 0:
+        scale = scale + abs(beta) * np.abs(np.asarray(Y0, np.float64))
+    for c in range(X.shape[1]):
+        err = rel_error(Y[:, c], Yref[:, c], scale[:, c])
+        assert err <= TOL[dtype], "column %d: relative error %g" % (c, err)
+
+
+def test_rmat_full():
+    """R-MAT scale 22 (67,108,864 nonzeros, FP32) in the encoding and launch
+    the benchmark uses: decode bit-exact on the device, every row of y within
+    2e-6 of the oracle, then y = -0.5 A x + 2 y."""
+    torch = need_gpu()
+    progress("generating R-MAT scale 22")
+    rp, ci, v = workloads.rmat(22)
+    n = 1 << 22
+    progress("encode R-MAT (automatic layout)")
+    A = P.Matrix.from_csr(rp, ci, v, n)
+    info = A.info()
+    progress("R-MAT layout %d T %d, %d escaped deltas" % (info["layout"], info["lane_nnz"], info["esc_delta"]))
+    assert info["esc_delta"] > 0
+    assert decode_equal(torch, A, rp, ci, v)
+    x = workloads.vector(n, 3, np.float32)
+    xd = torch.from_numpy(x).cuda()
+    progress("spmv R-MAT")
+    err = check_spmv(A.spmv(xd).cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, np.float32)
+    progress("R-MAT rel error %.3g" % err)
+    y0 = workloads.vector(n, 6, np.float32)
+    yd = torch.from_numpy(y0.copy()).cuda()
+    A.spmv(xd, yd, alpha=-0.5, beta=2.0)
+    check_spmv(yd.cpu().numpy(), rp, ci, v, x, y0, -0.5, 2.0, np.float32)
+
+
+def test_batch_full():
+    """The 64 uneven banded FP32 matrices (1k-64k rows) of the batched
+    benchmark in one persistent launch: every matrix's y against the oracle,
+    for alpha = 1, beta = 0 and for alpha = 0.75, beta = -1.5."""
+    torch = need_gpu()
+    progress("generating the 64-matrix batch")
+    mats = workloads.batch()
+    assert len(mats) == 64
+    enc = [P.Matrix.from_csr(c[0], c[1], c[2], m, layout="row") for m, c in mats]
+    B = P.Batch(enc)
+    xs = [workloads.vector(m, 100 + i, np.float32) for i, (m, _) in enumerate(mats)]
+    y0 = [workloads.vector(m, 200 + i, np.float32) for i, (m, _) in enumerate(mats)]
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    progress("batch spmv, alpha 1 beta 0")
+    ys = B.spmv(xd)
+    for (m, c), x, y in zip(mats, xs, ys):
+        check_spmv(y.cpu().numpy(), c[0], c[1], c[2], x, None, 1.0, 0.0, np.float32)
+    progress("batch spmv, alpha 0.75 beta -1.5")
+    yd = [torch.from_numpy(y.copy()).cuda() for y in y0]
+    B.spmv(xd, yd, alpha=0.75, beta=-1.5)
+    for (m, c), x, y, yy in zip(mats, xs, yd, y0):
+        check_spmv(y.cpu().numpy(), c[0], c[1], c[2], x, yy, 0.75, -1.5, np.float32)
