@@ -115,9 +115,30 @@ def time_steps(torch, fn, steps, warmup):
     return start.elapsed_time(end) / steps, wall
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the all-cores oracle run uses: the CPUs this process may run
+    on (the box's share, not every core of the host)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(W, seconds):
-    """The oracle (plain FP64 CSR SpMV in C, single thread) on the same
-    matrix, repeated for about `seconds`."""
+    """The oracle (plain FP64 CSR SpMV / SpMM in C, rows split over OpenMP
+    threads) on the same matrix: one thread, then every CPU this process may
+    use, each repeated for about seconds / 2."""
     import oracle
 
     rp, ci, v = W["rp"], W["ci"], W["v"]
@@ -129,17 +150,29 @@ def cpu_baseline(W, seconds):
         X = np.random.default_rng(0).uniform(-1, 1, (W["n"], W["k"]))
         fn = lambda: oracle.spmm(rp, ci, v, X)  # noqa: E731
         flops = 2.0 * len(ci) * W["k"]
-    fn()
-    reps, t0 = 0, time.perf_counter()
-    while True:
+
+    def run(threads):
+        oracle.set_threads(threads)
         fn()
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle FP64 CSR %s over the whole matrix, %d repetitions in %.1f s"
-                      % ("SpMV" if W["k"] == 1 else "SpMM", reps, el)}
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds / 2:
+                break
+        return flops * reps / el / 1e9, reps, el
+
+    one = run(1)
+    threads = host_threads()
+    many = run(threads)
+    oracle.set_threads(1)
+    kind = "SpMV" if W["k"] == 1 else "SpMM k=%d" % W["k"]
+    return {"value": many[0], "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "oracle FP64 CSR %s over the whole matrix: %d repetitions in %.1f s on %d threads, "
+                      "%d in %.1f s on one" % (kind, many[1], many[2], threads, one[1], one[2]),
+            "single_core": {"value": one[0], "cores": 1},
+            "cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def main():

@@ -33,10 +33,11 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (plain -O2, no vectorisation flags)."""
+    """Compile the C oracle with gcc (plain -O2, no vectorisation flags;
+    OpenMP only splits the rows of the two products over threads)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", "-fopenmp",
                                "-o", tmp, _SRC])
         os.replace(tmp, _SO)
     return _SO
@@ -48,6 +49,8 @@ def lib():
         build()
         L = ctypes.CDLL(_SO)
         P, I64, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads(1)
         L.oracle_csr_spmv_f64.argtypes = [I64, P, P, P, P, P, D, D]
         L.oracle_csr_absmv_f64.argtypes = [I64, P, P, P, P, P]
         L.oracle_csr_spmtv_f64.argtypes = [I64, I64, P, P, P, P, P, D, D]
@@ -70,6 +73,11 @@ def _p(a: np.ndarray):
 def _csr(row_ptr, col, val):
     return (np.ascontiguousarray(row_ptr, np.int32), np.ascontiguousarray(col, np.int32),
             np.ascontiguousarray(val, np.float64))
+
+
+def set_threads(t: int) -> None:
+    """Threads the SpMV / SpMM products split their rows over (default 1)."""
+    lib().oracle_set_threads(int(t))
 
 
 def spmv(row_ptr, col, val, x, y=None, alpha=1.0, beta=0.0):

@@ -33,6 +33,7 @@
  * The multiplicity fit here is deliberately simple (proportional with a cap),
  * not the library's: any valid table decodes the same way.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -51,12 +52,19 @@ enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EIO = 2, ORC_ECORRUPT = 3, ORC_ENOMEM = 4
 
 /* ======================================================================
  * SpMV family, plain definitions in double precision (Sec. III-A)
+ *
+ * Rows are independent, so the two products split their rows over the
+ * threads set by oracle_set_threads (1 unless the caller asks for more); a
+ * row's sum runs in the same order whatever the thread count.
  * ====================================================================== */
+
+void oracle_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
 
 void oracle_csr_spmv_f64(int64_t m, const int32_t *row_ptr, const int32_t *col,
                          const double *val, const double *x, double *y,
                          double alpha, double beta)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         double s = 0.0;
         for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
@@ -100,6 +108,7 @@ void oracle_csr_spmm_f64(int64_t m, int64_t k, const int32_t *row_ptr,
                          int64_t ldx, double *Y, int64_t ldy, double alpha,
                          double beta)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i)
         for (int64_t c = 0; c < k; ++c) {
             double s = 0.0;

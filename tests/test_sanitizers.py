@@ -36,6 +36,6 @@ def test_encoder_under_sanitizers(tmp_path):
 def test_oracle_under_sanitizers(tmp_path):
     exe = str(tmp_path / "orc")
     _run(["gcc", "-std=gnu11"] + SAN + [os.path.join(HERE, "oracle_roundtrip.c"),
-          os.path.join(ROOT, "oracle", "dtans_oracle.c"), "-o", exe], str(tmp_path))
+          os.path.join(ROOT, "oracle", "dtans_oracle.c"), "-fopenmp", "-o", exe], str(tmp_path))
     r = _run([exe, str(tmp_path / "rt.dtans")], str(tmp_path))
     assert " 0 failures" in r.stdout
