@@ -209,6 +209,25 @@ dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx
                         int64_t ldy, double alpha, double beta, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as dtans_spmm, on the same kernels, with the partial sums of rows
+ * split across lanes (nonzero-balanced layout) kept in a scratch array that
+ * the library itself holds, one per device (64 MiB, held from the first call
+ * on a device until the process ends) instead of the handle's scratch.  The
+ * call allocates nothing and never synchronizes; the matrix must be on the
+ * current device (dtans_to_device), and dtans_reserve is not needed.
+ * DTANS_ERANGE, before any launch, when the product needs more scratch than
+ * the array holds (2 * lanes * min(k, 32) doubles; nothing for the row
+ * layout).  Every call on one device shares that device's array and leaves
+ * its contents behind (each call writes every partial sum it reads), so
+ * calls that may overlap on one device (concurrent streams or threads)
+ * race: order them on one stream.
+ */
+dtans_status dtans_spmm_noalloc(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
+                                int64_t ldy, double alpha, double beta, void *stream);
+
+/*
  * Transposed product dX = alpha * A^T dY + beta * dX by decode-and-scatter of
  * the same streams.  When n x c values of dX (c up to 8) fit in LDS beside
  * the tables, every CU scatters into its own copy with LDS atomic adds and a

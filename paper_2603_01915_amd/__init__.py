@@ -306,6 +306,25 @@ class Matrix:
                                       alpha, beta, ctypes.c_void_p(_stream(stream))))
         return Y
 
+    def spmm_noalloc(self, X, Y, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """Y = alpha * A X + beta * Y through dtans_spmm_noalloc: no device
+        allocation (the library's per-device scratch array instead of the
+        handle's).  X [n, k] and Y [m, k] row-major, both given by the
+        caller; the matrix must already be on the device (``to_device``)."""
+        m, n = self.shape
+        _dev(X, self.torch_dtype, "X", 2)
+        if X.size(0) != n:
+            raise ValueError("X has %d rows, expected %d" % (X.size(0), n))
+        k = X.size(1)
+        _dev(Y, self.torch_dtype, "Y", 2)
+        if tuple(Y.shape) != (m, k):
+            raise ValueError("Y must be [%d, %d]" % (m, k))
+        if k == 0:
+            return Y
+        _lib.check(self._L.dtans_spmm_noalloc(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
+                                              alpha, beta, ctypes.c_void_p(_stream(stream))))
+        return Y
+
     def spmm_t(self, dY, dX=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
         """dX = alpha * A^T dY + beta * dX with dY [m, k] and dX [n, k]."""
         torch = _torch()

@@ -77,6 +77,7 @@ SIGNATURES = {
     "dtans_set_launch": (_I32, [_P, _I32, _I32, _I32]),
     "dtans_spmv": (_I32, [_P, _P, _P, _D, _D, _P]),
     "dtans_spmm": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
+    "dtans_spmm_noalloc": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
     "dtans_spmv_sym": (_I32, [_P, _P, _P, _P, _D, _D, _P]),
     "dtans_spmm_t": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
     "dtans_decode_csr": (_I32, [_P, _P, _P, _P, _P]),

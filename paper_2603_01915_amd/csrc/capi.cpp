@@ -748,19 +748,52 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     return DTANS_OK;
 }
 
+namespace {
+// argument checks shared by dtans_spmm and dtans_spmm_noalloc
+dtans_status spmm_args(const dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, const void *Y,
+                       int64_t ldy) {
+    const Container &c = mat->c;
+    if (ldx < k || ldy < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
+    if (ldx >= (1ll << 31) || ldy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
+    if ((c.m > 0 && !Y) || (c.n > 0 && c.nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
+    return DTANS_OK;
+}
+}  // namespace
+
 dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
                         int64_t ldy, double alpha, double beta, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
     dtans_status s = ready(mat, k);
     if (s) return s;
-    const Container &c = mat->c;
-    if (ldx < k || ldy < k) return set_err(DTANS_EINVAL, "leading dimensions must be >= k");
-    if (ldx >= (1ll << 31) || ldy >= (1ll << 31)) return set_err(DTANS_ERANGE, "leading dimensions must be below 2^31");
-    if ((c.m > 0 && !Y) || (c.n > 0 && c.nnz > 0 && !X)) return set_err(DTANS_EINVAL, "null vector");
-    hipError_t e = launch_spmm(mat->view, c.dtype == kF64, k, X, ldx, Y, ldy, alpha, beta,
+    s = spmm_args(mat, k, X, ldx, Y, ldy);
+    if (s) return s;
+    hipError_t e = launch_spmm(mat->view, mat->c.dtype == kF64, k, X, ldx, Y, ldy, alpha, beta,
                                (double *)mat->scratch, plan_launch(mat), st);
     if (e != hipSuccess) return hip_err(e, "dtans_spmm launch");
+    return DTANS_OK;
+}
+
+dtans_status dtans_spmm_noalloc(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
+                                int64_t ldy, double alpha, double beta, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be >= 1");
+    dtans_status s = ready(mat, 0);  // the handle's own scratch is not used
+    if (s) return s;
+    s = spmm_args(mat, k, X, ldx, Y, ldy);
+    if (s) return s;
+    const size_t need = spmm_scratch_bytes(mat->view, k);
+    if (need > kStaticScratchBytes)
+        return set_err(DTANS_ERANGE, "dtans_spmm_noalloc: this product needs " + std::to_string(need) +
+                                         " bytes of scratch, above the library's fixed " +
+                                         std::to_string(kStaticScratchBytes) +
+                                         " bytes; use dtans_spmm after dtans_reserve");
+    void *ptr = nullptr;
+    hipError_t e = static_scratch(&ptr);
+    if (e != hipSuccess) return hip_err(e, "dtans_spmm_noalloc scratch lookup");
+    e = launch_spmm(mat->view, mat->c.dtype == kF64, k, X, ldx, Y, ldy, alpha, beta, (double *)ptr,
+                    plan_launch(mat), st);
+    if (e != hipSuccess) return hip_err(e, "dtans_spmm_noalloc launch");
     return DTANS_OK;
 }
 

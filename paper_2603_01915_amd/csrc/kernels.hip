@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "dtans_core.hpp"
@@ -1710,6 +1711,34 @@ hipError_t launch_csr(const CsrDev &c, bool f64, int k, const void *X, int64_t l
                                 num_cus, st);
     return csr_impl<float>(c, k, (const float *)X, ldx, (float *)Y, ldy, alpha, beta, partial,
                            num_cus, st);
+}
+
+// Scratch for callers that cannot allocate device memory (dtans_spmm_noalloc):
+// a file-scope array that every GPU the library runs on holds from the first
+// use until the process ends.  On the host its name is only a stand-in
+// symbol, so host code never passes it to a kernel, a memset or a copy: it
+// looks up the device address of each GPU's own copy once, with that device
+// current, and passes that address instead.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace dtans

@@ -52,6 +52,12 @@ constexpr int kMaxPassCols = 32;
 // Device scratch launch_spmm needs for k columns: layout NNZ keeps a head and
 // a tail partial sum (double) per lane and column of a pass; 0 for layout ROW.
 size_t spmm_scratch_bytes(const DevMat &a, int k);
+// Size of the library-owned scratch array (one per device, kept until the
+// process ends) that dtans_spmm_noalloc uses instead of the handle's scratch.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+// Device address of the current device's copy of that array (looked up once
+// per device, then cached); never the array's host-side name.
+hipError_t static_scratch(void **ptr);
 // y = alpha*A*x + beta*y; k columns of X/Y (k = 1: SpMV); partial: device
 // scratch of at least spmm_scratch_bytes(a, k) bytes.
 hipError_t launch_spmm(const DevMat &a, bool f64, int k, const void *X, int64_t ldx, void *Y,
