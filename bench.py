@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--first-delta-column", action="store_true",
                     help="first delta of a row is its column (the paper's form) instead of "
                          "column - row + 2^29")
+    ap.add_argument("--max-mult", type=int, default=0,
+                    help="multiplicity cap of the alphabet fit (0: the library's 255; 256 is the paper's M)")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -240,7 +242,8 @@ def main():
     t0 = time.perf_counter()
     A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
                            waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu,
-                           stream_stage=args.stream_stage, first_delta_column=args.first_delta_column)
+                           stream_stage=args.stream_stage, first_delta_column=args.first_delta_column,
+                           max_mult=args.max_mult)
     enc_s = time.perf_counter() - t0
     info = A0.info()
     log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
@@ -291,6 +294,7 @@ def main():
                    "waves_per_wg": info["waves_per_wg"],
                    "stream_stage": {1: "direct", 2: "lds_ring"}[info["stream_stage"]],
                    "first_delta": "column" if info["first_delta_column"] else "column - row + 2^29",
+                   "max_mult": args.max_mult or 255, "direct_table": bool(info["direct_table"]),
                    "copies_rotated": copies},
         "compressed_GBps": round(achieved, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
@@ -331,6 +335,26 @@ def main():
                                "frac": round(cb / (cms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                                "copies_rotated": csr_copies}
         res["speedup_vs_csr"] = round(cms / ms, 3)
+        log("rocSPARSE baseline")
+        R = P.RocsparseBaseline(rp, ci, v, n)
+        Rs = [R] + [P.RocsparseBaseline(rp, ci, v, n) for _ in range(csr_copies - 1)]
+
+        def rstep(i):
+            j = i % csr_copies
+            if k == 1:
+                Rs[j].spmv(bx[j], by[j])
+            else:
+                Rs[j].spmm(bx[j], by[j])
+
+        rms, _ = time_steps(torch, rstep, args.steps, args.warmup)
+        res["rocsparse_baseline"] = {"ms": round(rms, 6), "GFLOP/s": round(flops / (rms * 1e-3) / 1e9, 3),
+                                     "GB/s": round(cb / (rms * 1e-3) / 1e9, 2),
+                                     "frac": round(cb / (rms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                     "alg": "csr_adaptive" if k == 1 else "spmm default (csr)",
+                                     "copies_rotated": csr_copies}
+        res["speedup_vs_rocsparse"] = round(rms / ms, 3)
+        for B_ in Rs:
+            B_.close()
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)

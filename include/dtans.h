@@ -301,6 +301,27 @@ int64_t dtans_csr_bytes(const dtans_csr *csr);
 void dtans_csr_destroy(dtans_csr *csr);
 
 /*
+ * The platform's own sparse library on the same CSR arrays, as context for
+ * the baselines above (rocSPARSE generic API: SpMV with the adaptive CSR
+ * algorithm, preprocessed once by dtans_rocsparse_create; SpMM with the
+ * library's default CSR algorithm, X and Y row-major).  Same argument
+ * conventions as dtans_csr_*.  dtans_rocsparse_create copies the host arrays
+ * to the current device and waits for it; the first dtans_rocsparse_spmm with
+ * a given k sizes the library's work buffer (it may allocate and wait), later
+ * calls with that k allocate nothing.  Not part of the compressed format's
+ * path; DTANS_EHIP carries rocSPARSE's status code.
+ */
+typedef struct dtans_rocsparse dtans_rocsparse;
+dtans_status dtans_rocsparse_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                    const int32_t *col_idx, const void *vals, dtans_dtype dtype,
+                                    dtans_rocsparse **out);
+dtans_status dtans_rocsparse_spmv(dtans_rocsparse *rs, const void *x, void *y, double alpha, double beta,
+                                  void *stream);
+dtans_status dtans_rocsparse_spmm(dtans_rocsparse *rs, int32_t k, const void *X, int64_t ldx, void *Y,
+                                  int64_t ldy, double alpha, double beta, void *stream);
+void dtans_rocsparse_destroy(dtans_rocsparse *rs);
+
+/*
  * Autotuner (encode-time parameters; no equivalent in the paper, which uses
  * one fixed launch per GPU).  Candidate options are the fields of *in left at
  * 0 / AUTO, searched over: layout {ROW, NNZ}; for NNZ, nonzeros per lane

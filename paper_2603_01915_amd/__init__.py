@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import (DtansError, EncodeOpts, Info, LAYOUT_AUTO, LAYOUT_NNZ, LAYOUT_ROW, STAGE_AUTO,
                    STAGE_DIRECT, STAGE_RING)
 
-__all__ = ["Matrix", "CsrBaseline", "Batch", "DtansError", "autotune", "autotune_candidates", "version",
+__all__ = ["Matrix", "CsrBaseline", "RocsparseBaseline", "Batch", "DtansError", "autotune", "autotune_candidates", "version",
            "LAYOUT_AUTO", "LAYOUT_ROW", "LAYOUT_NNZ", "STAGE_AUTO", "STAGE_DIRECT", "STAGE_RING"]
 
 _LAYOUTS = {"auto": LAYOUT_AUTO, "row": LAYOUT_ROW, "nnz": LAYOUT_NNZ,
@@ -360,25 +360,11 @@ class Matrix:
         return rp, ci[:self.nnz], v[:self.nnz]
 
 
-class CsrBaseline:
-    """Plain (uncompressed) CSR SpMV/SpMM on the same GPU, for comparison."""
+class _CsrProducts:
+    """Shape and dtype checks shared by the uncompressed baselines (the C ABI
+    cannot check the sizes of device buffers)."""
 
-    def __init__(self, row_ptr, col, vals, n: int, variant: int = 0):
-        self._L = _lib.load()
-        rp = _np(row_ptr, np.int32)
-        ci = _np(col, np.int32)
-        v = _np(vals)
-        self.shape = (len(rp) - 1, n)
-        self.nnz = len(ci)
-        self.is_f64 = v.dtype == np.float64
-        h = ctypes.c_void_p()
-        _lib.check(self._L.dtans_csr_create(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
-                                            _dtype_code(v), variant, ctypes.byref(h)))
-        self._h = h
-
-    @property
-    def bytes(self) -> int:
-        return int(self._L.dtans_csr_bytes(self._h))
+    _spmv_fn = _spmm_fn = None
 
     def spmv(self, x, y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
         torch = _torch()
@@ -393,8 +379,8 @@ class CsrBaseline:
         _dev(y, dt, "y", 1)
         if y.numel() != m:
             raise ValueError("y has %d entries, expected %d" % (y.numel(), m))
-        _lib.check(self._L.dtans_csr_spmv(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
-                                          ctypes.c_void_p(_stream(stream))))
+        _lib.check(getattr(self._L, self._spmv_fn)(self._h, x.data_ptr(), y.data_ptr(), alpha, beta,
+                                                    ctypes.c_void_p(_stream(stream))))
         return y
 
     def spmm(self, X, Y=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
@@ -413,20 +399,73 @@ class CsrBaseline:
             raise ValueError("Y must be [%d, %d]" % (m, k))
         if k == 0:
             return Y
-        _lib.check(self._L.dtans_csr_spmm(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
-                                          alpha, beta, ctypes.c_void_p(_stream(stream))))
+        _lib.check(getattr(self._L, self._spmm_fn)(self._h, k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
+                                                    alpha, beta, ctypes.c_void_p(_stream(stream))))
         return Y
-
-    def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            self._L.dtans_csr_destroy(self._h)
-            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+
+class CsrBaseline(_CsrProducts):
+    """Plain (uncompressed) CSR SpMV/SpMM on the same GPU, for comparison."""
+
+    _spmv_fn, _spmm_fn = "dtans_csr_spmv", "dtans_csr_spmm"
+
+    def __init__(self, row_ptr, col, vals, n: int, variant: int = 0):
+        self._L = _lib.load()
+        rp = _np(row_ptr, np.int32)
+        ci = _np(col, np.int32)
+        v = _np(vals)
+        self.shape = (len(rp) - 1, n)
+        self.nnz = len(ci)
+        self.is_f64 = v.dtype == np.float64
+        h = ctypes.c_void_p()
+        _lib.check(self._L.dtans_csr_create(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
+                                            _dtype_code(v), variant, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def bytes(self) -> int:
+        return int(self._L.dtans_csr_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.dtans_csr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+
+class RocsparseBaseline(_CsrProducts):
+    """The platform's sparse library (rocSPARSE) on the same CSR arrays, as
+    context for the plain CSR kernels; bytes as for CsrBaseline."""
+
+    _spmv_fn, _spmm_fn = "dtans_rocsparse_spmv", "dtans_rocsparse_spmm"
+
+    def __init__(self, row_ptr, col, vals, n: int):
+        self._L = _lib.load()
+        rp = _np(row_ptr, np.int32)
+        ci = _np(col, np.int32)
+        v = _np(vals)
+        self.shape = (len(rp) - 1, n)
+        self.nnz = len(ci)
+        self.is_f64 = v.dtype == np.float64
+        h = ctypes.c_void_p()
+        _lib.check(self._L.dtans_rocsparse_create(len(rp) - 1, n, len(ci), _ptr(rp), _ptr(ci), _ptr(v),
+                                                  _dtype_code(v), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def bytes(self) -> int:
+        m, _ = self.shape
+        return 4 * (m + 1) + self.nnz * (4 + (8 if self.is_f64 else 4))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.dtans_rocsparse_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
 
 class Batch:

@@ -89,6 +89,10 @@ SIGNATURES = {
     "dtans_csr_spmm": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
     "dtans_csr_bytes": (_I64, [_P]),
     "dtans_csr_destroy": (None, [_P]),
+    "dtans_rocsparse_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, _PP]),
+    "dtans_rocsparse_spmv": (_I32, [_P, _P, _P, _D, _D, _P]),
+    "dtans_rocsparse_spmm": (_I32, [_P, _I32, _P, _I64, _P, _I64, _D, _D, _P]),
+    "dtans_rocsparse_destroy": (None, [_P]),
     "dtans_autotune_candidates": (_I32, [_I64, _I64, _P, ctypes.c_int, _I32,
                                          ctypes.POINTER(EncodeOpts), ctypes.POINTER(EncodeOpts),
                                          _I32]),

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdtans.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["encoder.cpp", "capi.cpp", "kernels.hip", "encode_kernels.hip", "sym_kernels.hip"]
+SOURCES = ["encoder.cpp", "capi.cpp", "kernels.hip", "encode_kernels.hip", "sym_kernels.hip",
+           "rocsparse_baseline.cpp"]
 ARCH = "gfx950"
 
 
@@ -57,7 +58,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-lrocsparse"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("linking libdtans.so failed:\n" + res.stdout + res.stderr)

@@ -85,6 +85,14 @@ struct DevBufs {
 
 }  // namespace
 
+namespace dtans {
+// the thread-local error message, for the library's other source files
+dtans_status set_error(dtans_status s, const std::string &msg) { return set_err(s, msg); }
+}  // namespace dtans
+
+namespace {
+}  // namespace
+
 struct dtans_matrix {
     Container c;
     std::vector<uint64_t> gtab;
@@ -174,7 +182,7 @@ bool uses_ring(const dtans_matrix *h) {
 }
 
 // Default workgroup shape of the decode kernels: LDS admits 160 KiB /
-// table_bytes workgroups per CU (2 for FP64, 3 for FP32); the registers admit
+// table_bytes workgroups per CU (2 for FP64 and FP32); the registers admit
 // `per_simd` waves per SIMD (8 for the row-layout SpMV kernels, 7 for the
 // nonzero-balanced ones).  A workgroup's waves are dealt to the CU's 4 SIMDs,
 // so its size is kept a multiple of 4: with 9-wave workgroups, three per CU
@@ -182,7 +190,7 @@ bool uses_ring(const dtans_matrix *h) {
 // ended.  Among workgroup counts, the most resident waves win (then the most
 // workgroups).
 void default_shape(bool f64, int per_simd, int &wpw, int &wgcu) {
-    const int table_bytes = kSlots * (8 + (f64 ? 8 : 4));
+    const int table_bytes = kSlots * (8 + (f64 ? 12 : 8));
     const int maxwg = std::max(1, 160 * 1024 / table_bytes);
     wpw = 4;
     wgcu = 1;

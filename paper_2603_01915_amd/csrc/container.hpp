@@ -133,8 +133,9 @@ void nnz_layout_meta(const Container &c, std::vector<int32_t> &lane_row,
                      std::vector<int32_t> &split_row, std::vector<int32_t> &split_first,
                      std::vector<int32_t> &split_last);
 
-// GPU table: one 64-bit entry per slot (see dtans_core.hpp) + one value per slot
-// returns true for "direct" tables (every base at most 255)
+// Device tables (see dtans_core.hpp): one 64-bit column-delta entry per slot
+// and one value entry per slot (value bits + metadata, 12 bytes for FP64, 8
+// for FP32); returns true for "direct" tables (every base at most 255)
 bool gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values);
 
 }  // namespace dtans

@@ -20,15 +20,7 @@
 //    worked example in Sec. IV-D);
 //  * a lane's last segment performs no checks and no loads (Sec. IV-F).
 //
-// GPU table entry (one 64-bit word per slot, shared by both alphabets):
-//   bits  0..29  column delta of the delta-table slot
-//   bit   30     the value-table slot holds the escape symbol
-//   bit   31     the delta-table slot holds the escape symbol
-//   bits 32..47  delta slot:  (base - 1) | digit << 8
-//   bits 48..63  value slot:  (base - 1) | digit << 8
-// plus one value (float or double) per slot in a second array.  When every
-// base of both tables is at most 255 ("direct" tables) the two metadata
-// fields hold base | digit << 8 instead (unused slots: base 1).
+// Device tables: see "Device tables of the HIP kernels" below.
 #pragma once
 
 #include <stdint.h>
@@ -111,59 +103,81 @@ DTANS_HD bool append_and_check(uint32_t &d, uint32_t &r, uint32_t D, uint32_t Rm
     return extract;
 }
 
-// The same two steps for tables whose bases are all at most 255 (an encoder
-// multiplicity cap of 255 instead of M = 256): the GPU entry then holds the
-// base itself in the low byte of a slot's metadata (base | digit << 8), so
-// no +1 is needed, and R = product of the bases < 2^32 needs no wrap.
-DTANS_HD void group4_direct(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, uint32_t &D,
-                            uint32_t &R) {
-    const uint32_t b1 = m1 & 0xffu, b2 = m2 & 0xffu, b3 = m3 & 0xffu;
-    const uint32_t b23 = b2 * b3;
-    const uint32_t lo = meta_digit(m2) * b3 + meta_digit(m3);
-    const uint32_t hi = meta_digit(m0) * b1 + meta_digit(m1);
-    D = hi * b23 + lo;
-    R = (m0 & 0xffu) * b1 * b23;
+// ---------------------------------------------------------------------------
+// Device tables of the HIP kernels.  Per slot, the column-delta table holds a
+// 64-bit entry: the delta (low word; 0 for the escape symbol) and the
+// metadata (b - 1) | d << 16 | escape << 31; the value table holds the
+// value's bits and the metadata b | d << 16 | escape << 31 (b the slot's
+// base, at most 256, d its digit; unused slots have b = 1, d = 0).  The two
+// metadata words are laid out so that one packed 16-bit multiply-add turns a
+// (delta, value) pair of symbols into its digit pair and base product.
+constexpr uint32_t kMetaEscape = 1u << 31;
+
+// (R, D) of one nonzero's two symbols, delta s (meta (b_s - 1) | d_s << 16)
+// then value t (meta b_t | d_t << 16), as (lo, hi) 16-bit halves:
+// lo = (b_s - 1) b_t + b_t = b_s b_t, hi = d_s b_t + d_t (the value's digit is
+// the less significant one).  Exact when every base is at most 255 (both
+// results are below 2^16); escape bits must be clear.
+DTANS_HD uint32_t pair_rd_ref(uint32_t ms, uint32_t mt) {
+    const uint32_t bs1 = ms & 0xffffu, ds = ms >> 16, bt = mt & 0xffffu, dt = mt >> 16;
+    return ((bs1 * bt + bt) & 0xffffu) | (((ds * bt + dt) & 0xffffu) << 16);
+}
+
+// A group of two nonzeros (symbols 1-4 or 5-8 of a segment) from the (R, D)
+// pairs A (first nonzero) and B: D = D_A R_B + D_B, R = R_A R_B.
+DTANS_HD void group_pairs_ref(uint32_t A, uint32_t B, uint32_t &D, uint32_t &R) {
+    D = (A >> 16) * (B & 0xffffu) + (B >> 16);
+    R = (A & 0xffffu) * (B & 0xffffu);
+}
+
+// The same group for tables with a base of 256 (16-bit halves would wrap):
+// metadata of symbols 1-4 in stream order (delta, value, delta, value), D as
+// above and Rm1 = R - 1 modulo 2^32 (R is at most 2^32).
+DTANS_HD void group_general(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, uint32_t &D,
+                            uint32_t &Rm1) {
+    const uint32_t b0 = (m0 & 0xffffu) + 1u, b1 = m1 & 0xffffu;
+    const uint32_t b2 = (m2 & 0xffffu) + 1u, b3 = m3 & 0xffffu;
+    const uint32_t d0 = (m0 >> 16) & 0xffu, d1 = (m1 >> 16) & 0xffu;
+    const uint32_t d2 = (m2 >> 16) & 0xffu, d3 = (m3 >> 16) & 0xffu;
+    D = ((d0 * b1 + d1) * b2 + d2) * b3 + d3;  // < R <= 2^32
+    Rm1 = b0 * b1 * b2 * b3 - 1u;              // wraps exactly when R = 2^32
 }
 
 #if defined(__HIPCC__) || defined(__HIP__)
-// group4_direct from the high words of the four symbols' table entries
-// (delta symbols 1 and 3 hold base | digit << 8 in bits 0..15, value symbols
-// 2 and 4 in bits 16..31), on packed 16-bit lanes: v_perm gathers the bytes
-// into (u16, u16) pairs, one packed multiply-add forms both two-digit parts
-// and one packed multiply both two-base products, and a dot product joins
-// them.  Same D and R as group4_direct (all intermediate values < 2^16).
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void group4_packed(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t h3,
-                                              uint32_t &D, uint32_t &R) {
-    const uint32_t P = __builtin_amdgcn_perm(h3, h1, 0x0c060c02u);  // (b1, b3)
-    const uint32_t Q = __builtin_amdgcn_perm(h2, h0, 0x0c050c01u);  // (d0, d2)
-    const uint32_t S = __builtin_amdgcn_perm(h3, h1, 0x0c070c03u);  // (d1, d3)
-    const uint32_t B = __builtin_amdgcn_perm(h2, h0, 0x0c040c00u);  // (b0, b2)
-    const u16x2 T = __builtin_bit_cast(u16x2, Q) * __builtin_bit_cast(u16x2, P) +
-                    __builtin_bit_cast(u16x2, S);                     // (d0 b1 + d1, d2 b3 + d3)
-    const u16x2 U = __builtin_bit_cast(u16x2, B) * __builtin_bit_cast(u16x2, P);  // (b0 b1, b2 b3)
-    const uint32_t V = __builtin_amdgcn_perm(1u, __builtin_bit_cast(uint32_t, U), 0x0c040302u);  // (b2 b3, 1)
-    D = __builtin_amdgcn_udot2(T, __builtin_bit_cast(u16x2, V), 0u, false);
-    R = __umul24((uint32_t)U.x, (uint32_t)U.y);
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+// pair_rd_ref as one v_pk_mad_u16 (the value's base broadcast to both halves)
+__device__ __forceinline__ uint32_t pair_rd(uint32_t ms, uint32_t mt) {
+    const u16x2 a = as_u16x2(ms), b = as_u16x2(mt);
+    return as_u32(a * b.xx + b);
+}
+
+// group_pairs_ref: (D_A, 1) formed by one v_perm, D by one 16-bit dot product,
+// R by one 24-bit multiply of the low halves
+__device__ __forceinline__ void group_pairs(uint32_t A, uint32_t B, uint32_t &D, uint32_t &R) {
+    const uint32_t U = __builtin_amdgcn_perm(1u, A, 0x0c040302u);  // (D_A, 1)
+    D = __builtin_amdgcn_udot2(as_u16x2(U), as_u16x2(B), 0u, false);
+    R = __umul24(A & 0xffffu, B & 0xffffu);
     // R < 2^32 is used as a 32-bit factor of the 64-bit state products; the
     // empty asm keeps the compiler from widening it to a 48-bit product
-    // (which would double the 64-bit multiplies of append_direct)
+    // (which would double the 64-bit multiplies of append_word)
     asm("" : "+v"(R));
 }
 #endif
 
-DTANS_HD bool append_direct(uint32_t &d, uint32_t &r, uint32_t D, uint32_t R, uint32_t &word) {
+// Append a digit group (D, R) of a direct table (R = product of bases < 2^32)
+// to the state (d, r) and run the check: true when the word is extracted
+// from the state.  The extracted word is written either way (the caller uses
+// it only then), which saves a select.
+DTANS_HD bool append_word(uint32_t &d, uint32_t &r, uint32_t D, uint32_t R, uint32_t &word) {
     const uint64_t r64 = (uint64_t)r * R;
     const uint64_t d64 = (uint64_t)d * R + D;
     const bool extract = (r64 >> 32) != 0;
-    if (extract) {
-        word = (uint32_t)d64;
-        d = (uint32_t)(d64 >> 32);
-        r = (uint32_t)(r64 >> 32);
-    } else {
-        d = (uint32_t)d64;
-        r = (uint32_t)r64;
-    }
+    word = (uint32_t)d64;
+    d = extract ? (uint32_t)(d64 >> 32) : (uint32_t)d64;
+    r = extract ? (uint32_t)(r64 >> 32) : (uint32_t)r64;
     return extract;
 }
 

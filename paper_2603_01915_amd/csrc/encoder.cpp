@@ -934,37 +934,34 @@ void nnz_layout_meta(const Container &c, std::vector<int32_t> &lane_row,
 }
 
 bool gpu_table(const Container &c, std::vector<uint64_t> &entry, std::vector<uint8_t> &values) {
+    // column-delta table: delta | ((b - 1) | d << 16 | escape << 31) << 32;
+    // value table: value bits, then b | d << 16 | escape << 31 (12 bytes per
+    // slot for FP64, 8 for FP32); unused slots: b = 1, d = 0
     entry.assign(kSlots, 0);
-    const size_t vb = c.value_bytes();
-    values.assign(kSlots * vb, 0);
+    const size_t vb = c.value_bytes(), stride = vb + 4;
+    values.assign(kSlots * stride, 0);
     bool direct = true;
     for (int i = 0; i < kSlots; ++i) {
         if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))
             direct = false;
-    }
-    // base - 1 (general) or the base itself (direct); unused slots: base 1
-    auto meta = [&](uint32_t base, uint32_t digit) -> uint64_t {
-        return (direct ? base : base - 1) | (digit << 8);
-    };
-    for (int i = 0; i < kSlots; ++i) {
         uint64_t e = 0;
-        e |= meta(1, 0) << 32;
-        e |= meta(1, 0) << 48;
         if (c.dtab.flags[i] & 1) {
-            e &= ~(0xffffull << 32);
-            e |= (c.dtab.flags[i] & 2) ? (1ull << 31) : (c.dtab.sym[i] & (kDeltaLimit - 1));
-            e |= meta(c.dtab.base[i], c.dtab.digit[i]) << 32;
-        }
-        if (c.vtab.flags[i] & 1) {
-            e &= ~(0xffffull << 48);
-            if (c.vtab.flags[i] & 2) e |= 1ull << 30;
-            e |= meta(c.vtab.base[i], c.vtab.digit[i]) << 48;
-            if (!(c.vtab.flags[i] & 2)) {
-                if (vb == 8) memcpy(&values[8 * i], &c.vtab.sym[i], 8);
-                else { uint32_t x = (uint32_t)c.vtab.sym[i]; memcpy(&values[4 * i], &x, 4); }
-            }
+            const bool esc = (c.dtab.flags[i] & 2) != 0;
+            const uint32_t meta = (c.dtab.base[i] - 1) | (c.dtab.digit[i] << 16) | (esc ? kMetaEscape : 0u);
+            e = (esc ? 0u : (uint32_t)c.dtab.sym[i]) | ((uint64_t)meta << 32);
         }
         entry[i] = e;
+        uint32_t vmeta = 1;
+        uint8_t *dst = &values[stride * i];
+        if (c.vtab.flags[i] & 1) {
+            const bool esc = (c.vtab.flags[i] & 2) != 0;
+            vmeta = c.vtab.base[i] | (c.vtab.digit[i] << 16) | (esc ? kMetaEscape : 0u);
+            if (!esc) {
+                if (vb == 8) memcpy(dst, &c.vtab.sym[i], 8);
+                else { uint32_t x = (uint32_t)c.vtab.sym[i]; memcpy(dst, &x, 4); }
+            }
+        }
+        memcpy(dst + vb, &vmeta, 4);
     }
     return direct;
 }

@@ -55,6 +55,32 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
     return ((const VT *)p)[i];
 }
 
+// Value-table entry (device memory and LDS): the value's bits, then the slot's
+// metadata b | d << 16 | escape << 31 (see dtans_core.hpp).  12 bytes for
+// double: a value read is then two dword reads and the metadata a third, at
+// 12 * slot, instead of a second table at another stride.
+template <typename VT> struct VEntry;
+template <> struct VEntry<double> {
+    uint32_t lo, hi, meta;
+    __device__ __forceinline__ double value() const {
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    }
+};
+template <> struct VEntry<float> {
+    uint32_t bits, meta;
+    __device__ __forceinline__ float value() const { return __builtin_bit_cast(float, bits); }
+};
+
+// Both coding tables in LDS, the value table first so that every read of
+// either has a constant offset below 2^16 (FP64: 48 + 32 KiB, FP32: 32 + 32).
+template <typename VT> struct Tables {
+    VEntry<VT> tv[kSlots];
+    uint64_t td[kSlots];
+};
+static_assert(sizeof(VEntry<double>) == 12 && sizeof(VEntry<float>) == 8, "value entry sizes");
+static_assert(sizeof(Tables<double>) == kSlots * 20 && sizeof(Tables<float>) == kSlots * 16,
+              "tables are two packed arrays");
+
 // ------------------------------------------------------------------ sinks
 // A sink consumes one lane's decoded nonzeros a segment at a time:
 //   segment<MULTI>(col, v, nreal, g, rowk): nonzeros k < nreal with columns
@@ -67,6 +93,9 @@ __device__ __forceinline__ VT load_value(const void *p, uint64_t i) {
 //     wavefront together at the end of an encoded wave; `row` holds the live
 //     lane's last nonzeros, `kind` how the lane holds it (kComplete, kHead,
 //     kTail or kMid).
+//   col_scale(params): the decoder multiplies every column delta by it, so
+//     that col[k] arrives as column * col_scale modulo 2^32 (e.g. the byte
+//     offset of x[column], which saves a shift per gather).
 // Rows that end in the middle of a lane are finished inside segment().  Rows
 // without nonzeros are a lane of their own in the row layout (finish_row with
 // no segment) and never visited in the nonzero layout.
@@ -151,11 +180,13 @@ struct SpmmSink {
     }
     // called once per decoding step before the step issues any loads
     __device__ __forceinline__ void pre_step() { consume(); }
-    // UNIT: x spans at most 4 GiB, so a 32-bit byte offset from the uniform
-    // base addresses it (one shift per gather, base in SGPRs)
+    // UNIT: x spans at most 4 GiB, so columns arrive as 32-bit byte offsets
+    // from the uniform base (the decoder scales the deltas; base in SGPRs)
+    static __device__ __forceinline__ uint32_t col_scale(const Params &) {
+        return UNIT ? (uint32_t)sizeof(VT) : 1u;
+    }
     __device__ __forceinline__ const VT *xrow(uint32_t col) const {
-        return UNIT ? (const VT *)((const char *)p.X + col * (uint32_t)sizeof(VT))
-                    : p.X + (uint64_t)col * p.ldx;
+        return UNIT ? (const VT *)((const char *)p.X + col) : p.X + (uint64_t)col * p.ldx;
     }
     __device__ __forceinline__ void store(int32_t row, int kind) {
         if (kind == kComplete) {
@@ -214,6 +245,25 @@ struct SpmmSink {
                 for (int k = 0; k < 4; ++k)
 #pragma unroll
                     for (int c = 0; c < KC; ++c) acc[c] = fma((ACC)v[k], (ACC)x[k][c], acc[c]);
+                return;
+            }
+            if constexpr (!MULTI) {
+                // single-row lanes: only a lane's last segment is short (or it
+                // has none left); column 0 stands in for the missing nonzeros,
+                // whose products are dropped by a select, with no branches
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t cc = k < nreal ? col[k] : 0u;
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) x[k][c] = xrow(cc)[c];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) {
+                        const ACC t = fma((ACC)v[k], (ACC)x[k][c], acc[c]);
+                        acc[c] = k < nreal ? t : acc[c];
+                    }
                 return;
             }
 #pragma unroll
@@ -305,6 +355,7 @@ struct TransSink {
     const Params p;
     int32_t cur;
     VT dy[KC];
+    static __device__ __forceinline__ uint32_t col_scale(const Params &) { return 1u; }
     __device__ TransSink(const Params &pp, int64_t, int32_t first_row, bool) : p(pp), cur(-1) {
         (void)first_row;
     }
@@ -350,6 +401,7 @@ struct TransLdsSink {
     const Params p;
     int32_t cur;
     VT dy[KC];
+    static __device__ __forceinline__ uint32_t col_scale(const Params &) { return 1u; }
     __device__ TransLdsSink(const Params &pp, int64_t, int32_t, bool) : p(pp), cur(-1) {}
     __device__ __forceinline__ void load_row(int32_t row) {
         cur = row;
@@ -382,6 +434,7 @@ struct DecodeSink {
         typename Bits<VT>::T *vals;
     };
     const Params p;
+    static __device__ __forceinline__ uint32_t col_scale(const Params &) { return 1u; }
     __device__ DecodeSink(const Params &pp, int64_t, int32_t, bool) : p(pp) {}
     template <bool MULTI>
     __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
@@ -417,6 +470,11 @@ struct GlobalWords {
     __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
         const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
         return *(const uint32_t *)(W + (p + 4 * lane_prefix(mask)));
+    }
+    // the same when every lane of the wavefront reads (prefix = lane)
+    __device__ __forceinline__ uint32_t read_lanes(uint32_t pos, uint32_t lane) const {
+        const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
+        return *(const uint32_t *)(W + (p + 4 * lane));
     }
     // Nothing in the memory system fetches a stream ahead of its reads, so
     // every step's words would come from HBM.  Once the first words are
@@ -503,6 +561,10 @@ struct RingWords {
         const uint32_t *at = ring + (((pos + skew) >> 2) & (kRing - 1));
         return at[lane_prefix(mask)];
     }
+    __device__ __forceinline__ uint32_t read_lanes(uint32_t pos, uint32_t ln) const {
+        const uint32_t *at = ring + (((pos + skew) >> 2) & (kRing - 1));
+        return at[ln];
+    }
     __device__ __forceinline__ uint32_t prefetch(uint32_t, uint32_t) const { return 0u; }
     __device__ __forceinline__ void retire(uint32_t) const {}
     __device__ __forceinline__ void step_begin() {
@@ -584,14 +646,34 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
     return q;
 }
 
+// LDS byte offsets of a segment's eight slots (unpack8 of dtans_core.hpp
+// with the entry sizes folded in): delta slots i1, i3, i5, i7 into the delta
+// table (8-byte entries), value slots i2, i4, i6, i8 into the value table
+// (E-byte entries), straight from the three words.
+template <int E>
+__device__ __forceinline__ void slot_offsets(uint32_t w1, uint32_t w2, uint32_t w3, uint32_t od[4],
+                                             uint32_t ov[4]) {
+    od[0] = (w3 << 3) & 0x7ff8u;                                  // i1 = w3[0:12]
+    ov[0] = ((w3 >> 12) & 0xfffu) * E;                             // i2 = w3[12:24]
+    od[1] = __builtin_amdgcn_alignbit(w2, w3, 21) & 0x7ff8u;       // i3 = w3[24:32] | w2[0:4] << 8
+    ov[1] = ((w2 >> 4) & 0xfffu) * E;                              // i4 = w2[4:16]
+    od[2] = (w2 >> 13) & 0x7ff8u;                                  // i5 = w2[16:28]
+    ov[2] = (__builtin_amdgcn_alignbit(w1, w2, 28) & 0xfffu) * E;  // i6 = w2[28:32] | w1[0:8] << 4
+    od[3] = (w1 >> 5) & 0x7ff8u;                                   // i7 = w1[8:20]
+    ov[3] = (w1 >> 20) * E;                                        // i8 = w1[20:32]
+}
+
 // Decode encoded wave `slice` (lanes slice*64 .. slice*64+63) and feed the
 // nonzeros of this thread's lane to a sink constructed here.
-// TF, the table format: 0 bases stored minus one (see dtans_core.hpp); 1
-// "direct" tables (every base at most 255, stored as is); 2 direct tables
-// without an escape symbol in either alphabet (no escape checks at all)
+// TF, the table format: 0 some base is 256 (the paper's M; a digit group's
+// base product may reach 2^32); 1 "direct" tables (every base at most 255: a
+// group's arithmetic runs on packed 16-bit halves); 2 direct tables without
+// an escape symbol in either alphabet (no escape checks at all).
+// A step of the whole wavefront is "full" when every lane decodes four
+// nonzeros and has a next segment (no masks, every lane loads its words);
+// other steps handle lanes that end, are short or have nothing left.
 template <int LAYOUT, typename VT, class Sink, class Src, int TF>
-__device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__restrict__ tab,
-                                             const VT *__restrict__ tval, int64_t slice,
+__device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &tb, int64_t slice,
                                              uint32_t lane, const typename Sink::Params &sp,
                                              Src &src, Cursor<VT> &cur, const LaneGeo &geo) {
     const int64_t l = slice * kWave + lane;
@@ -601,7 +683,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
     int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, krow = geo.krow;
     int2 n1 = geo.n1, n2 = geo.n2;
     Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
+    const uint32_t scale = Sink::col_scale(sp);  // column deltas arrive multiplied by it
     const int S = (cnt + 3) >> 2;
+    const int F = min(S - 1, cnt >> 2);  // steps j < F: four nonzeros and a next segment
 
     // stream offsets are 32-bit and wave-uniform (popcounts of ballots), so
     // they live in SGPRs
@@ -626,75 +710,78 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         src.consumed(pos);
     }
     const uint32_t pf = src.prefetch(pos, lane);
-    uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row);
+    uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row) * scale;
     int64_t g = g0;
-    // the loop runs while some lane has a segment left (a uniform ballot test,
-    // no cross-lane reduction at the wave's start)
-    for (int j = 0; ballot(j < S) != 0; ++j) {
-        const bool act = j < S;
-        const bool more = j + 1 < S;
+
+    auto step = [&](auto fullc, int j) {
+        constexpr bool FULL = decltype(fullc)::value;
+        const bool act = FULL || j < S;
+        const bool more = FULL || j + 1 < S;
         const int rem = cnt - 4 * j;
-        uint32_t sl[8];
-        unpack8(e1 ? x1 : l1, e2 ? x2 : l2, l3, sl);
-        uint64_t e[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) e[k] = tab[sl[k]];
+        uint32_t od[4], ov[4];
+        slot_offsets<(int)sizeof(VEntry<VT>)>(e1 ? x1 : l1, e2 ? x2 : l2, l3, od, ov);
+        uint32_t dl[4], md[4], mv[4];
         VT v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = tval[sl[2 * k + 1]];
-        // Escapes first (their loads are issued before the next words, so
-        // waiting for them does not wait for the words).  Escape flags: bit 31
-        // of a delta slot's entry, bit 30 of a value slot's entry.  When no
-        // active lane has either bit set in any of its eight entries (the
-        // common case) the low words are the deltas as they are; otherwise the
-        // flags are masked off and the escapes read.  Padding symbols are
-        // never escapes, so only lanes past their last segment need masking.
-        uint32_t dl[4];
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t e = *(const uint64_t *)((const char *)tb.td + od[k]);
+            const VEntry<VT> ve = *(const VEntry<VT> *)((const char *)tb.tv + ov[k]);
+            dl[k] = (uint32_t)e;
+            md[k] = (uint32_t)(e >> 32);
+            v[k] = ve.value();
+            mv[k] = ve.meta;
+        }
+        // Escapes (their loads issued before the next words, so that waiting
+        // for them does not wait for the words): flagged by bit 31 of a slot's
+        // metadata.  When no active lane has a flag in any of its eight
+        // entries (the common case) nothing is masked; padding symbols are
+        // never escapes, so only lanes past their last segment can hold one
+        // otherwise.
+        if constexpr (TF != 2) {
+            const uint32_t fl = md[0] | md[1] | md[2] | md[3] | mv[0] | mv[1] | mv[2] | mv[3];
+            if ((FULL ? ~0ull : ballot(act)) & ballot((int32_t)fl < 0)) {  // uniform
 #pragma unroll
-        for (int k = 0; k < 4; ++k) dl[k] = (uint32_t)e[2 * k];
-        const uint32_t flags = (uint32_t)e[0] | (uint32_t)e[1] | (uint32_t)e[2] | (uint32_t)e[3] |
-                               (uint32_t)e[4] | (uint32_t)e[5] | (uint32_t)e[6] | (uint32_t)e[7];
-        if (TF != 2 && (ballot(act) & ballot(flags >= kDeltaLimit))) {  // uniform
+                for (int k = 0; k < 4; ++k) {
+                    const bool f = act && k < rem && (int32_t)md[k] < 0;
+                    const uint64_t mk = ballot(f);
+                    if (f) dl[k] = ED[dpos + lane_prefix(mk)] * scale;
+                    dpos += (uint32_t)__popcll(mk);
+                }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dl[k] &= kDeltaLimit - 1;
+                for (int k = 0; k < 4; ++k) {
+                    const bool f = act && k < rem && (int32_t)mv[k] < 0;
+                    const uint64_t mk = ballot(f);
+                    if (f) v[k] = EV[vpos + lane_prefix(mk)];
+                    vpos += (uint32_t)__popcll(mk);
+                }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool f = act && k < rem && ((uint32_t)e[2 * k] >> 31);
-                const uint64_t mk = ballot(f);
-                if (f) dl[k] = ED[dpos + lane_prefix(mk)];
-                dpos += (uint32_t)__popcll(mk);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool f = act && k < rem && (((uint32_t)e[2 * k + 1] >> 30) & 1u);
-                const uint64_t mk = ballot(f);
-                if (f) v[k] = EV[vpos + lane_prefix(mk)];
-                vpos += (uint32_t)__popcll(mk);
+                for (int k = 0; k < 4; ++k) {
+                    md[k] &= ~kMetaEscape;
+                    mv[k] &= ~kMetaEscape;
+                }
             }
         }
-        // The next segment's words, in flight while this segment's x gathers
-        // are served.  The loads are issued on every step, so that the wait
+        // the two digit groups and their checks (Alg. 3), then the next
+        // segment's words, in flight while this segment's x gathers are
+        // served.  The loads are issued on every step, so that the wait
         // counts of the loads before them are the same on every path; lanes
         // that do not load (all of them on a wave's last step) read a
         // neighbouring word of the stream, whose value is not used.
-        const uint64_t m3 = ballot(more);  // lanes that load this step's words
+        const uint64_t m3 = FULL ? ~0ull : ballot(more);  // lanes that load this step's words
         uint64_t m1 = 0, m2 = 0;
-        if (m3) {
+        if (FULL || m3) {
             uint32_t D, R;
-            auto group = [&](int q, uint32_t &x) {
-                if constexpr (TF >= 1) {
-                    group4_packed((uint32_t)(e[q] >> 32), (uint32_t)(e[q + 1] >> 32),
-                                  (uint32_t)(e[q + 2] >> 32), (uint32_t)(e[q + 3] >> 32), D, R);
-                    return append_direct(d, r, D, R, x);
-                } else {
-                    const uint32_t m0 = (uint32_t)(e[q] >> 32) & 0xffffu, m1 = (uint32_t)(e[q + 1] >> 48);
-                    const uint32_t m2 = (uint32_t)(e[q + 2] >> 32) & 0xffffu, m3 = (uint32_t)(e[q + 3] >> 48);
-                    group4(m0, m1, m2, m3, D, R);
-                    return append_and_check(d, r, D, R, x);
-                }
-            };
-            e1 = group(0, x1);
-            e2 = group(4, x2);
+            if constexpr (TF >= 1) {
+                group_pairs(pair_rd(md[0], mv[0]), pair_rd(md[1], mv[1]), D, R);
+                e1 = append_word(d, r, D, R, x1);
+                group_pairs(pair_rd(md[2], mv[2]), pair_rd(md[3], mv[3]), D, R);
+                e2 = append_word(d, r, D, R, x2);
+            } else {
+                group_general(md[0], mv[0], md[1], mv[1], D, R);
+                e1 = append_and_check(d, r, D, R, x1);
+                group_general(md[2], mv[2], md[3], mv[3], D, R);
+                e2 = append_and_check(d, r, D, R, x2);
+            }
             // masks combined on the scalar unit: a ballot of a plain compare
             // is the compare's own lane mask
             m1 = m3 & ~ballot(e1);
@@ -704,8 +791,13 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             const uint32_t c1 = 4 * (uint32_t)__popcll(m1), c2 = 4 * (uint32_t)__popcll(m2);
             l1 = src.read(pos, m1);
             l2 = src.read(pos + c1, m2);
-            l3 = src.read(pos + c1 + c2, m3);
-            pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
+            if constexpr (FULL) {
+                l3 = src.read_lanes(pos + c1 + c2, lane);
+                pos += c1 + c2 + 4 * kWave;
+            } else {
+                l3 = src.read(pos + c1 + c2, m3);
+                pos += c1 + c2 + 4 * (uint32_t)__popcll(m3);
+            }
         }
         // deferred products of the previous step and the ring's pending chunk,
         // then the next chunk and this step's x loads, which the next step
@@ -713,7 +805,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
         sink.pre_step();
         src.step_begin();
         src.consumed(pos);
-        const int nreal = act ? min(rem, 4) : 0;
+        const int nreal = FULL ? 4 : (act ? min(rem, 4) : 0);
         uint32_t cols[4];
         int32_t rowk[4];
         if constexpr (LAYOUT == 1) {
@@ -737,7 +829,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
                     row_end = n1.y;
                     n1 = n2;
                     n2 = a.nzr[min((int64_t)krow + 2, a.n_nzr)];
-                    col = first_base(a.first_mode, (uint32_t)row);
+                    col = first_base(a.first_mode, (uint32_t)row) * scale;
                 }
                 col += dl[k];
                 cols[k] = col;
@@ -746,7 +838,17 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
             sink.template segment<true>(cols, v, nreal, g, rowk);
         }
         g += 4;
+    };
+    // full steps while every lane of the wavefront has one (a uniform test),
+    // then the rest with per-lane masks
+    int j = 0;
+    if (ballot(0 < F) == ~0ull) {
+        do {
+            step(std::true_type(), j);
+            ++j;
+        } while (ballot(j < F) == ~0ull);
     }
+    for (; ballot(j < S) != 0; ++j) step(std::false_type(), j);
     src.retire(pf);
     cur.pos = pos;
     cur.dpos = dpos;
@@ -765,37 +867,46 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const uint64_t *__
 
 // one encoded wave read straight from device memory
 template <int LAYOUT, typename VT, class Sink, int TF>
-__device__ __forceinline__ void decode_slice_global(const DevMat &a, const uint64_t *tab,
-                                                    const VT *tval, int64_t slice, uint32_t lane,
+__device__ __forceinline__ void decode_slice_global(const DevMat &a, const Tables<VT> &tb,
+                                                    int64_t slice, uint32_t lane,
                                                     const typename Sink::Params &sp) {
     const uint64_t wo = uniform_load(a.woff + slice), we = uniform_load(a.woff + slice + 1);
     GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
     Cursor<VT> cur{0, 0, 0, a.escd + uniform_load(a.doff + slice),
                    (const VT *)a.escv + uniform_load(a.voff + slice)};
     const LaneGeo geo = lane_geo<LAYOUT>(a, slice, lane, lane_first_row<LAYOUT>(a, slice, lane));
-    decode_slice<LAYOUT, VT, Sink, GlobalWords, TF>(a, tab, tval, slice, lane, sp, src, cur, geo);
+    decode_slice<LAYOUT, VT, Sink, GlobalWords, TF>(a, tb, slice, lane, sp, src, cur, geo);
 }
 
 // Both tables into LDS in 16-byte pieces, every piece of a pass loaded before
-// any is stored, so that a pass costs one memory round trip (one pass for a
-// 1024-thread workgroup).
+// any is stored, so that a pass costs one memory round trip (two passes for a
+// 1024-thread workgroup); the column deltas are multiplied by `scale` on the
+// way (the sink's col_scale).
 template <typename VT>
-__device__ __forceinline__ void stage_tables(const DevMat &a, uint64_t *s_tab, VT *s_val) {
-    constexpr int kT = kSlots * 8 / 16, kV = kSlots * (int)sizeof(VT) / 16;  // kV <= kT
-    const uint4 *gt = (const uint4 *)a.tab, *gv = (const uint4 *)a.tabval;
-    uint4 *lt = (uint4 *)s_tab, *lv = (uint4 *)s_val;
+__device__ __forceinline__ void stage_tables(const DevMat &a, Tables<VT> &tb, uint32_t scale) {
+    constexpr int kV = kSlots * (int)sizeof(VEntry<VT>) / 16, kT = kSlots * 8 / 16;
+    constexpr int kAll = kV + kT, kU = 4;  // pieces per thread and pass
+    const uint4 *gv = (const uint4 *)a.tabval, *gt = (const uint4 *)a.tab;
+    uint4 *lds = (uint4 *)&tb;  // tv, then td
     const int nt = blockDim.x;
-    for (int b = 0; b < kT; b += 2 * nt) {
-        const int i0 = b + (int)threadIdx.x, i1 = i0 + nt;
-        uint4 t0 = make_uint4(0, 0, 0, 0), t1 = t0, v0 = t0, v1 = t0;
-        if (i0 < kT) t0 = gt[i0];
-        if (i1 < kT) t1 = gt[i1];
-        if (i0 < kV) v0 = gv[i0];
-        if (i1 < kV) v1 = gv[i1];
-        if (i0 < kT) lt[i0] = t0;
-        if (i1 < kT) lt[i1] = t1;
-        if (i0 < kV) lv[i0] = v0;
-        if (i1 < kV) lv[i1] = v1;
+    for (int b = 0; b < kAll; b += kU * nt) {
+        uint4 t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = b + u * nt + (int)threadIdx.x;
+            t[u] = make_uint4(0, 0, 0, 0);
+            if (i < kV) t[u] = gv[i];
+            else if (i < kAll) {
+                t[u] = gt[i - kV];
+                t[u].x *= scale;  // two entries per piece: {delta, meta}, {delta, meta}
+                t[u].z *= scale;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = b + u * nt + (int)threadIdx.x;
+            if (i < kAll) lds[i] = t[u];
+        }
     }
     __syncthreads();
 }
@@ -805,12 +916,14 @@ __device__ __forceinline__ void stage_tables(const DevMat &a, uint64_t *s_tab, V
 // arbiter otherwise favours the oldest wavefronts, which then finish their
 // (equal) shares early and leave the younger ones to end the launch at low
 // occupancy; ranking by remaining work keeps the wavefronts of a CU in step.
+// (The quarter is found by comparisons, not a 64-bit division, which would
+// cost a hundred scalar instructions per wave.)
 __device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t total) {
-    const int64_t pr = total > 0 ? ((remaining - 1) * 4) / total : 0;
-    if (pr >= 3) __builtin_amdgcn_s_setprio(3);
-    else if (pr == 2) __builtin_amdgcn_s_setprio(2);
-    else if (pr == 1) __builtin_amdgcn_s_setprio(1);
-    else __builtin_amdgcn_s_setprio(0);
+    const int64_t q = (remaining - 1) * 4;  // quarter = floor(q / total)
+    if (total <= 0 || q < total) __builtin_amdgcn_s_setprio(0);
+    else if (q < 2 * total) __builtin_amdgcn_s_setprio(1);
+    else if (q < 3 * total) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(3);
 }
 
 // The row-layout sweep of decode_kernel over waves s0, s0 + stride, ... below
@@ -819,7 +932,7 @@ __device__ __forceinline__ void set_progress_priority(int64_t remaining, int64_t
 // workgroup (its previous matrix), then stage them (the whole workgroup
 // passes the same value).
 template <typename VT, class Sink, int TF>
-__device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT *s_val,
+__device__ __forceinline__ void decode_rows(const DevMat &a, Tables<VT> &tb,
                                             uint32_t lane, const typename Sink::Params &sp,
                                             int64_t s_end, int64_t s0, int64_t stride,
                                             int64_t share, int stage = 1) {
@@ -836,7 +949,7 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
     uint64_t wo = uniform_load(a.woff + sf), we = uniform_load(a.woff + sf + 1);
     uint64_t dof = uniform_load(a.doff + sf), vof = uniform_load(a.voff + sf);
     if (stage == 2) __syncthreads();
-    if (stage) stage_tables<VT>(a, s_tab, s_val);
+    if (stage) stage_tables<VT>(a, tb, Sink::col_scale(sp));
     int64_t k = 0;
     for (int64_t s = s0; s < s_end; s += stride, ++k) {
         const int64_t s1 = s + stride < s_end ? s + stride : s;
@@ -846,7 +959,7 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
         GlobalWords src{(const char *)(a.words + wo), 4 * (we - wo)};
         Cursor<VT> cur{0, 0, 0, a.escd + dof, (const VT *)a.escv + vof};
         set_progress_priority(share - k, share);
-        decode_slice<1, VT, Sink, GlobalWords, TF>(a, s_tab, s_val, s, lane, sp, src, cur, geo);
+        decode_slice<1, VT, Sink, GlobalWords, TF>(a, tb, s, lane, sp, src, cur, geo);
         geo = next;
         wo = wo1;
         we = we1;
@@ -856,10 +969,10 @@ __device__ __forceinline__ void decode_rows(const DevMat &a, uint64_t *s_tab, VT
 }
 
 // The sweep of one persistent workgroup over its encoded waves (tables
-// staged into s_tab / s_val on the way).
+// staged into LDS on the way).
 template <int LAYOUT, typename VT, class Sink, int TF>
 __device__ __forceinline__ void decode_sweep(const DevMat &a, const typename Sink::Params &sp,
-                                             uint64_t *s_tab, VT *s_val) {
+                                             Tables<VT> &tb) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t total = (int64_t)gridDim.x * wpb;
@@ -878,14 +991,14 @@ __device__ __forceinline__ void decode_sweep(const DevMat &a, const typename Sin
     const int64_t s0 = s_begin + pos_in_xcd * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t share = s0 < s_end ? (s_end - 1 - s0) / stride + 1 : 0;  // encoded waves of this wavefront
     if constexpr (LAYOUT == 2) {
-        stage_tables<VT>(a, s_tab, s_val);
+        stage_tables<VT>(a, tb, Sink::col_scale(sp));
         // long lanes: a wave's start-up is a small part of its work
         for (int64_t s = s0, k = 0; s < s_end; s += stride, ++k) {
             set_progress_priority(share - k, share);
-            decode_slice_global<LAYOUT, VT, Sink, TF>(a, s_tab, s_val, s, lane, sp);
+            decode_slice_global<LAYOUT, VT, Sink, TF>(a, tb, s, lane, sp);
         }
     } else {
-        decode_rows<VT, Sink, TF>(a, s_tab, s_val, lane, sp, s_end, s0, stride, share);
+        decode_rows<VT, Sink, TF>(a, tb, lane, sp, s_end, s0, stride, share);
     }
 }
 
@@ -893,9 +1006,8 @@ __device__ __forceinline__ void decode_sweep(const DevMat &a, const typename Sin
 // 16-wave workgroups share a CU, which is what the LDS tables permit)
 template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
 __global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
-    __shared__ uint64_t s_tab[kSlots];
-    __shared__ VT s_val[kSlots];
-    decode_sweep<LAYOUT, VT, Sink, TF>(a, sp, s_tab, s_val);
+    __shared__ __align__(16) Tables<VT> tb;
+    decode_sweep<LAYOUT, VT, Sink, TF>(a, sp, tb);
 }
 
 // Transposed product with dX privatised in LDS: a workgroup (one per CU)
@@ -907,8 +1019,7 @@ template <int LAYOUT, typename VT, int KC, int TF>
 __global__ __launch_bounds__(1024, 4) void trans_lds_kernel(DevMat a,
                                                             typename TransLdsSink<VT, KC>::Params sp,
                                                             VT *part) {
-    __shared__ uint64_t s_tab[kSlots];
-    __shared__ VT s_val[kSlots];
+    __shared__ __align__(16) Tables<VT> tb;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     VT *s_dx = (VT *)s_dyn;
     const int64_t cnt = a.n * KC, slots = lds_slot((uint32_t)cnt);
@@ -917,7 +1028,7 @@ __global__ __launch_bounds__(1024, 4) void trans_lds_kernel(DevMat a,
     // orders these stores before the first scatter)
     typename TransLdsSink<VT, KC>::Params q = sp;
     q.lds = s_dx;
-    decode_sweep<LAYOUT, VT, TransLdsSink<VT, KC>, TF>(a, q, s_tab, s_val);
+    decode_sweep<LAYOUT, VT, TransLdsSink<VT, KC>, TF>(a, q, tb);
     __syncthreads();
     VT *dst = part + (int64_t)blockIdx.x * cnt;
     for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) dst[i] = s_dx[lds_slot((uint32_t)i)];
@@ -948,10 +1059,9 @@ __global__ __launch_bounds__(256) void trans_reduce_kernel(const VT *part, int64
 // rows an XCD works on within a window of its share.
 template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
 __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sink::Params sp) {
-    __shared__ uint64_t s_tab[kSlots];
-    __shared__ VT s_val[kSlots];
+    __shared__ __align__(16) Tables<VT> tb;
     extern __shared__ uint32_t s_ring[];  // RingWords<kRingWords>::kWords per wavefront
-    stage_tables<VT>(a, s_tab, s_val);
+    stage_tables<VT>(a, tb, Sink::col_scale(sp));
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int64_t wpb = blockDim.x / kWave;
     const int64_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -979,8 +1089,7 @@ __global__ __launch_bounds__(1024, MINW) void ring_kernel(DevMat a, typename Sin
         const int32_t fr2 = s + 2 < sb ? lane_first_row<LAYOUT>(a, s + 2, lane) : 0;
         LaneGeo next{0, 0, 0, 0, 0, 0};
         if (s + 1 < sb) next = lane_geo<LAYOUT>(a, s + 1, lane, fr1);
-        decode_slice<LAYOUT, VT, Sink, RingWords<kRingWords>, TF>(a, s_tab, s_val, s, lane, sp, src, cur,
-                                                                 geo);
+        decode_slice<LAYOUT, VT, Sink, RingWords<kRingWords>, TF>(a, tb, s, lane, sp, src, cur, geo);
         geo = next;
         fr1 = fr2;
     }
@@ -1121,8 +1230,7 @@ __global__ void empty_rows_kernel(const int32_t *rows, int64_t count, VT *Y, int
 // ------------------------------------------------- multi-matrix launch
 template <typename VT>
 __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha, double beta) {
-    __shared__ uint64_t s_tab[kSlots];
-    __shared__ VT s_val[kSlots];
+    __shared__ __align__(16) Tables<VT> tb;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), wpb = blockDim.x / kWave;
     const int t0 = b.wg_task[blockIdx.x], t1 = b.wg_task[blockIdx.x + 1];
@@ -1145,11 +1253,9 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         const int64_t s0 = task.first_wave + wib, s_end = (int64_t)task.first_wave + task.num_waves;
         const int64_t share = s0 < s_end ? (s_end - 1 - s0) / wpb + 1 : 0;
         if (a.base_direct)
-            decode_rows<VT, SpmmSink<VT, 1, true>, 1>(a, s_tab, s_val, lane, sp, s_end, s0, wpb, share,
-                                                       stage);
+            decode_rows<VT, SpmmSink<VT, 1, true>, 1>(a, tb, lane, sp, s_end, s0, wpb, share, stage);
         else
-            decode_rows<VT, SpmmSink<VT, 1, true>, 0>(a, s_tab, s_val, lane, sp, s_end, s0, wpb, share,
-                                                       stage);
+            decode_rows<VT, SpmmSink<VT, 1, true>, 0>(a, tb, lane, sp, s_end, s0, wpb, share, stage);
     }
 }
 
@@ -1501,7 +1607,7 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
 // LDS beside the tables, one 1024-thread workgroup per CU.
 template <typename VT>
 int trans_lds_cols(const DevMat &a) {
-    const int64_t room = 160 * 1024 - 1024 - (int64_t)kSlots * (8 + (int64_t)sizeof(VT));
+    const int64_t room = 160 * 1024 - 1024 - (int64_t)sizeof(Tables<VT>);
     for (int c : {8, 4, 2, 1})
         if ((a.n * c + a.n * c / 32 + 1) * (int64_t)sizeof(VT) <= room && a.n * c < (1ll << 31)) return c;
     return 0;

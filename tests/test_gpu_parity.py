@@ -267,6 +267,34 @@ def test_csr_baseline_parity(variant, dtype):
             check_spmv(Y[:, c], rp, ci, v, X[:, c], None, 1.0, 0.0, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_rocsparse_baseline_parity(dtype):
+    """The rocSPARSE context baseline computes the same products (SpMV and
+    SpMM with beta != 0); its tolerance is the same as ours, since the
+    library accumulates in the value type (FP32 sums are checked with the
+    FP32 bound only up to the row lengths of these cases)."""
+    torch = need_gpu()
+    for name, rp, ci, v, n in CASES:
+        v = v.astype(dtype)
+        m = len(rp) - 1
+        progress("rocsparse baseline %s %s" % (name, dtype.__name__))
+        R = P.RocsparseBaseline(rp, ci, v, n)
+        x = workloads.vector(n, 7, dtype)
+        y0 = workloads.vector(m, 8, dtype)
+        y = torch.from_numpy(y0.copy()).cuda()
+        R.spmv(torch.from_numpy(x).cuda(), y, alpha=0.5, beta=2.0)
+        y_ref = oracle.spmv(rp, ci, v, x, y0, alpha=0.5, beta=2.0)
+        scale = 0.5 * oracle.absmv(rp, ci, v, x) + 2.0 * np.abs(y0.astype(np.float64))
+        tol = 1e-12 if dtype == np.float64 else 2e-6 * max(1, int(np.diff(rp).max()) // 16)
+        assert rel_error(y.cpu().numpy(), y_ref, scale) <= tol
+        X = workloads.vector(n, 4, dtype, k=8)
+        Y = R.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+        Yref = oracle.spmm(rp, ci, v, X)
+        for c in range(8):
+            assert rel_error(Y[:, c], Yref[:, c], oracle.absmv(rp, ci, v, X[:, c])) <= tol
+        R.close()
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_batch_matches_single(dtype):
     torch = need_gpu()
