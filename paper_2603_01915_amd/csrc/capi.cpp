@@ -222,6 +222,7 @@ Launch plan_launch(const dtans_matrix *h) {
     // ring kernels: 16-wave workgroups unless set, as many per CU as fit
     L.ring_waves_per_wg = h->waves_per_wg > 0 ? h->waves_per_wg : 16;
     L.wg_per_cu = h->wg_per_cu;
+    L.fixed_shape = (h->waves_per_wg > 0 || h->wg_per_cu > 0) ? 1 : 0;
     return L;
 }
 

@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "dtans_core.hpp"
 #include "kernels.hpp"
@@ -114,6 +116,7 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // may cross rows, and the rows of the deferred nonzeros are kept with them.
 template <typename VT, int KC, bool UNIT, typename ACC = double, int DEFER = 0>
 struct SpmmSink {
+    static constexpr bool kCoop = false;
     static_assert(!DEFER || KC <= 4, "deferred products keep 4*KC x values in registers");
     static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
     struct Params {
@@ -341,9 +344,209 @@ struct SpmmSink {
     }
 };
 
+// A 32-bit value of lane `src` (all lanes of the wavefront active)
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+template <typename T>
+__device__ __forceinline__ T lane_value_of(T v, uint32_t src) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint64_t r = (uint64_t)lane_value((uint32_t)b, src) |
+                           ((uint64_t)lane_value((uint32_t)(b >> 32), src) << 32);
+        return __builtin_bit_cast(T, r);
+    } else {
+        return __builtin_bit_cast(T, lane_value(__builtin_bit_cast(uint32_t, v), src));
+    }
+}
+
+// Y (KC = G * CL columns) = alpha * A X + beta * Y with G lanes per row of X.
+// The 64 lanes of a wavefront form 64 / G groups; group q keeps, in G slots,
+// the sums of the streams q*G .. q*G + G - 1 (slot i: stream q*G + i), each
+// lane for CL = 16 / sizeof(VT) consecutive columns (one 16-byte load per
+// nonzero).  A step's (column, value) pairs move from the decoding lane to
+// its group with ds_bpermute, so that one load instruction reads 64 / G whole
+// rows of X (the address unit takes one cache line of an instruction at a
+// time: rows read one per lane cost a line per lane).  Columns arrive as byte
+// offsets of rows of X (col_scale = ldx * sizeof(VT)); X and Y rows are
+// 16-byte aligned.  Rows split over lanes give the same partial sums as
+// SpmmSink (tail and head slots; the middle pieces of a row summed per
+// wavefront into the head slot of the stretch's first stream), so the same
+// fix-up finishes them.
+template <typename VT, int G, typename ACC = double>
+struct CoopSpmmSink {
+    static constexpr bool kCoop = true;
+    static constexpr int CL = 16 / (int)sizeof(VT), KC = G * CL, NG = kWave / G;
+    static constexpr int kOcc = 4;
+    static_assert(G == 2 || G == 4 || G == 8, "2, 4 or 8 lanes per row of X");
+    struct Params {
+        const VT *X;
+        uint32_t ldx;
+        VT *Y;
+        uint32_t ldy;
+        double *partial;  // [lane][head/tail][KC]
+        double alpha, beta;
+    };
+    const Params p;
+    uint32_t grp, part;      // group, column chunk of this lane
+    int64_t wave0;           // global index of stream 0 of the wave
+    ACC acc[G][CL];
+    int32_t cur[G];          // row being summed in slot i (-1 before the first nonzero)
+    int32_t head_row[G];     // the slot's first row when it began before the stream, else -1
+    int32_t last;            // row of this lane's last nonzero so far (-1 before the first)
+
+    static __device__ __forceinline__ uint32_t col_scale(const Params &pp) {
+        return pp.ldx * (uint32_t)sizeof(VT);
+    }
+    __device__ CoopSpmmSink(const Params &pp, int64_t l, int32_t first_row, bool first_is_head) : p(pp) {
+        const uint32_t lane = (uint32_t)l & (kWave - 1);
+        grp = lane / G;
+        part = lane % G;
+        wave0 = l - lane;
+        last = -1;
+        const int32_t hr = first_is_head ? first_row : -1;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const uint32_t src = grp * G + i;
+            cur[i] = -1;
+            head_row[i] = (int32_t)lane_value((uint32_t)hr, src);
+#pragma unroll
+            for (int c = 0; c < CL; ++c) acc[i][c] = (ACC)0;
+        }
+    }
+    __device__ __forceinline__ void pre_step() {}
+    __device__ __forceinline__ VT *yrow(int32_t row) const {
+        return p.Y + (uint64_t)(uint32_t)row * p.ldy + part * CL;
+    }
+    __device__ __forceinline__ double *slot(int64_t stream, int kind) const {
+        return p.partial + (2 * stream + (kind == kTail ? 1 : 0)) * KC + part * CL;
+    }
+    // store slot i's sums for `row` (kind as for SpmmSink::store) and clear them
+    __device__ __forceinline__ void store(int i, int32_t row, int kind) {
+        if (kind == kComplete) {
+            VT *y = yrow(row);
+#pragma unroll
+            for (int c = 0; c < CL; ++c)
+                y[c] = (VT)(p.beta == 0.0 ? p.alpha * (double)acc[i][c]
+                                          : p.alpha * (double)acc[i][c] + p.beta * (double)y[c]);
+        } else {
+            double *q = slot(wave0 + grp * G + i, kind);
+#pragma unroll
+            for (int c = 0; c < CL; ++c) q[c] = (double)acc[i][c];
+        }
+#pragma unroll
+        for (int c = 0; c < CL; ++c) acc[i][c] = (ACC)0;
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal, int64_t,
+                                            const int32_t rowk[4]) {
+        // some stream reaches a row it did not end the last step in (a
+        // uniform test); otherwise the slots' rows stay as they are
+        const bool moved = MULTI && ballot(nreal > 0 && rowk[nreal - 1] != last) != 0;
+        if (MULTI && nreal > 0) last = rowk[nreal - 1];
+        int nr[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) nr[i] = (int)lane_value((uint32_t)nreal, grp * G + i);
+        // rounds r = 4 i + j (nonzero j of slot i's stream), each row of X
+        // requested kAhead rounds before it is multiplied
+        constexpr int R = 4 * G, kAhead = 2;
+        uint4 xs[kAhead];
+        VT vv[kAhead];
+        int32_t rk[kAhead];
+        auto fetch = [&](int r) {
+            const int b = r % kAhead, i = r >> 2, j = r & 3;
+            const uint32_t src = grp * G + i;
+            const uint32_t cj = lane_value(col[j], src);
+            vv[b] = lane_value_of(v[j], src);
+            if (MULTI && moved) rk[b] = (int32_t)lane_value((uint32_t)rowk[j], src);
+            // nonzeros past a stream's end read row 0 of X (their products are dropped)
+            xs[b] = *(const uint4 *)((const char *)p.X + (j < nr[i] ? cj : 0u) + part * 16);
+        };
+#pragma unroll
+        for (int r = 0; r < kAhead && r < R; ++r) fetch(r);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int b = r % kAhead, i = r >> 2, j = r & 3;
+            VT x[CL];
+            __builtin_memcpy(x, &xs[b], 16);
+            const VT vr = vv[b];
+            const int32_t rr = (MULTI && moved) ? rk[b] : 0;
+            if (r + kAhead < R) fetch(r + kAhead);
+            if (j < nr[i]) {
+                if (MULTI && moved && rr != cur[i]) {
+                    if (cur[i] >= 0) store(i, cur[i], cur[i] == head_row[i] ? kHead : kComplete);
+                    cur[i] = rr;
+                }
+#pragma unroll
+                for (int c = 0; c < CL; ++c) acc[i][c] = fma((ACC)vr, (ACC)x[c], acc[i][c]);
+            }
+        }
+    }
+    // single-row streams (row layout): every lane calls this at the end of the
+    // wave; `live` lanes' rows are complete
+    __device__ __forceinline__ void finish_row(int32_t row, int kind) { finish_all(row, kind, true); }
+    __device__ __forceinline__ void finish_lane(int32_t row, int kind, bool live) { finish_all(row, kind, live); }
+
+    __device__ __forceinline__ void finish_all(int32_t row, int kind, bool live) {
+        int32_t rw[G], key[G];
+        int kd[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const uint32_t src = grp * G + i;
+            rw[i] = (int32_t)lane_value((uint32_t)row, src);
+            kd[i] = (int)lane_value((uint32_t)(live ? kind : -1), src);
+            key[i] = kd[i] == kMid ? rw[i] : -1;
+        }
+        // non-middle pieces: complete rows to Y, heads and tails to their slots
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            if (kd[i] >= 0 && kd[i] != kMid) store(i, rw[i], kd[i]);
+        // middle pieces: suffix sums over the wave's streams in order (slots
+        // of a group, then groups), keyed by row (rows never decrease along
+        // the streams, so equal keys far apart mean the whole stretch holds
+        // that row); the first stream of each stretch stores the total
+#pragma unroll
+        for (int i = G - 2; i >= 0; --i)
+            if (key[i] >= 0 && key[i + 1] == key[i]) {
+#pragma unroll
+                for (int c = 0; c < CL; ++c) acc[i][c] += acc[i + 1][c];
+            }
+        const int32_t k0 = key[0];
+        const int32_t kn = (int32_t)lane_value((uint32_t)k0, ((grp + 1) % NG) * G + part);
+        const int32_t kprev = (int32_t)lane_value((uint32_t)key[G - 1], ((grp + NG - 1) % NG) * G + part);
+        bool kok[6];  // the cross-group steps that join equal keys
+#pragma unroll
+        for (int t = 0, d = 1; d < NG; d <<= 1, ++t) {
+            const int32_t kdn = (int32_t)lane_value((uint32_t)k0, ((grp + d) % NG) * G + part);
+            kok[t] = k0 >= 0 && grp + d < (uint32_t)NG && kdn == k0;
+        }
+#pragma unroll
+        for (int c = 0; c < CL; ++c) {
+            ACC V = acc[0][c];
+#pragma unroll
+            for (int t = 0, d = 1; d < NG; d <<= 1, ++t) {
+                const ACC u = lane_value_of(V, ((grp + d) % NG) * G + part);
+                if (kok[t]) V += u;
+            }
+            // the next group's slot-0 total
+            const ACC Vn = lane_value_of(V, ((grp + 1) % NG) * G + part);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (key[i] < 0) continue;
+                const bool first = i > 0 ? key[i - 1] != key[i] : (grp == 0 || kprev != key[i]);
+                if (!first) continue;
+                const bool more = key[G - 1] == key[i] && grp + 1 < (uint32_t)NG && kn == key[i];
+                const ACC tot = i == 0 ? V : acc[i][c] + (more ? Vn : (ACC)0);
+                slot(wave0 + grp * G + i, kHead)[c] = (double)tot;
+            }
+        }
+    }
+};
+
 // dX (k columns) += alpha * A^T dY, scattered with atomic adds.
 template <typename VT, int KC>
 struct TransSink {
+    static constexpr bool kCoop = false;
     static constexpr int kOcc = KC <= 2 ? 8 : 4;
     struct Params {
         const VT *dY;
@@ -392,6 +595,7 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 5); 
 // alpha is applied when the copies are summed
 template <typename VT, int KC>
 struct TransLdsSink {
+    static constexpr bool kCoop = false;
     static constexpr int kOcc = 4;
     struct Params {
         const VT *dY;
@@ -428,6 +632,7 @@ struct TransLdsSink {
 // decode to CSR: column and value bits of every nonzero
 template <typename VT>
 struct DecodeSink {
+    static constexpr bool kCoop = false;
     static constexpr int kOcc = 8;
     struct Params {
         int32_t *col;
@@ -854,7 +1059,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
     cur.dpos = dpos;
     cur.vpos = vpos;
     if constexpr (LAYOUT == 1) {
-        if (live && l < a.m) sink.finish_row(row, kComplete);
+        // (a cooperative sink needs every lane of the wavefront)
+        if constexpr (Sink::kCoop) sink.finish_lane(row, kComplete, live && l < a.m);
+        else if (live && l < a.m) sink.finish_row(row, kComplete);
     } else {
         // `row` holds this lane's last nonzeros: complete when it ends here;
         // started in an earlier lane, a head when it ends here, else a
@@ -1467,10 +1674,50 @@ K pick_tf(const DevMat &a, K direct_noesc, K direct, K general) {
     return a.base_direct ? (a.no_escape ? direct_noesc : direct) : general;
 }
 
+// Launch of a persistent direct-read decode kernel.  Unless the caller fixed
+// the shape, the workgroup size (16, 12, 8 or 4 waves: multiples of the
+// CU's 4 SIMDs) is the one that keeps the most wavefronts resident according
+// to the runtime's occupancy for this kernel, whose registers and LDS both
+// limit it (a 12-wave workgroup of a kernel that fits 4 waves per SIMD would
+// leave a CU with one workgroup, 3 waves per SIMD); cached per kernel.
+struct Shape {
+    int wpw, per_cu;
+};
+template <typename K>
+Shape fit_shape(K kern, const Launch &L) {
+    if (L.fixed_shape) return Shape{L.waves_per_wg, std::max(1, (L.grid + L.num_cus - 1) / L.num_cus)};
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, Shape>> cache;
+    const void *key = (const void *)kern;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto &c : cache)
+        if (c.first == key) return c.second;
+    Shape best{L.waves_per_wg, std::max(1, (L.grid + L.num_cus - 1) / L.num_cus)};
+    int best_res = 0;
+    for (int w : {16, 12, 8, 4}) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * w, 0) != hipSuccess) continue;
+        if (nb * w > best_res) {
+            best_res = nb * w;
+            best = Shape{w, nb};
+        }
+    }
+    cache.emplace_back(key, best);
+    return best;
+}
+
+template <typename K, typename... Args>
+hipError_t launch_persistent(K kern, const DevMat &a, const Launch &L, hipStream_t st, Args... args) {
+    const Shape sh = fit_shape(kern, L);
+    const int64_t need = (a.num_waves + sh.wpw - 1) / sh.wpw;
+    const int64_t grid = L.fixed_shape ? L.grid : std::min<int64_t>((int64_t)L.num_cus * sh.per_cu, need);
+    hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(1, grid)), dim3(64 * sh.wpw), 0, st, args...);
+    return hipGetLastError();
+}
+
 template <typename VT>
 hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, int64_t ldy,
                      double alpha, double beta, double *partial, Launch L, hipStream_t st) {
-    const dim3 block(64 * L.waves_per_wg);
     if (a.nnz == 0 || a.num_waves == 0) {
         if (a.m == 0) return hipSuccess;
         return for_kc(k, [&](auto KCc, int c0) {
@@ -1491,15 +1738,13 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         sp.partial = partial;
         sp.alpha = alpha;
         sp.beta = beta;
-        if (a.layout == 1)
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, SinkT, SinkT::kOcc, 1>,
-                                       decode_kernel<1, VT, SinkT, SinkT::kOcc, 0>),
-                               dim3(L.grid), block, 0, st, a, sp);
-        else
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 1>,
-                                       decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 0>),
-                               dim3(L.grid), block, 0, st, a, sp);
-        hipError_t e = hipGetLastError();
+        hipError_t e = a.layout == 1
+                           ? launch_persistent(pick_bd(a, decode_kernel<1, VT, SinkT, SinkT::kOcc, 1>,
+                                                       decode_kernel<1, VT, SinkT, SinkT::kOcc, 0>),
+                                               a, L, st, a, sp)
+                           : launch_persistent(pick_bd(a, decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 1>,
+                                                       decode_kernel<2, VT, SinkT, occ_nnz(SinkT::kOcc), 0>),
+                                               a, L, st, a, sp);
         if (e != hipSuccess || a.layout != 2) return e;
         return nnz_epilogue(a, partial, KC, Y + c0, ldy, alpha, beta, st);
     };
@@ -1574,17 +1819,40 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         sp.alpha = alpha;
         sp.beta = beta;
         constexpr int occ = SinkT::kOcc, occn = occ_nnz(SinkT::kOcc);
-        if (a.layout == 1)
-            hipLaunchKernelGGL(pick_tf(a, decode_kernel<1, VT, SinkT, occ, 2>, decode_kernel<1, VT, SinkT, occ, 1>,
-                                       decode_kernel<1, VT, SinkT, occ, 0>),
-                               dim3(L.grid), block, 0, st, a, sp);
-        else
-            hipLaunchKernelGGL(pick_tf(a, decode_kernel<2, VT, SinkT, occn, 2>, decode_kernel<2, VT, SinkT, occn, 1>,
-                                       decode_kernel<2, VT, SinkT, occn, 0>),
-                               dim3(L.grid), block, 0, st, a, sp);
-        hipError_t e = hipGetLastError();
+        hipError_t e =
+            a.layout == 1
+                ? launch_persistent(pick_tf(a, decode_kernel<1, VT, SinkT, occ, 2>, decode_kernel<1, VT, SinkT, occ, 1>,
+                                            decode_kernel<1, VT, SinkT, occ, 0>),
+                                    a, L, st, a, sp)
+                : launch_persistent(pick_tf(a, decode_kernel<2, VT, SinkT, occn, 2>, decode_kernel<2, VT, SinkT, occn, 1>,
+                                            decode_kernel<2, VT, SinkT, occn, 0>),
+                                    a, L, st, a, sp);
         if (e != hipSuccess || a.layout != 2) return e;
         return nnz_epilogue(a, partial, 1, Y, ldy, alpha, beta, st);
+    }
+    // Several columns: groups of lanes share each row of X (CoopSpmmSink) when
+    // its rows can be read as aligned 16-byte pieces at 32-bit byte offsets;
+    // chunks of 8 / 16 / 32 FP32 or 4 / 8 FP64 columns, the rest as below.
+    const bool coop = (uintptr_t)X % 16 == 0 && (ldx * (int64_t)sizeof(VT)) % 16 == 0 &&
+                      a.n * ldx * (int64_t)sizeof(VT) <= (1ll << 32);
+    if (coop) {
+        constexpr int CLv = 16 / (int)sizeof(VT);
+        int c0 = 0;
+        hipError_t e = hipSuccess;
+        while (e == hipSuccess && k - c0 >= 2 * CLv) {
+            const int left = k - c0;
+            if (left >= 4 * CLv) {
+                e = launch(TypeBox<CoopSpmmSink<VT, 4>>(), 4 * CLv, c0);
+                c0 += 4 * CLv;
+            } else {
+                e = launch(TypeBox<CoopSpmmSink<VT, 2>>(), 2 * CLv, c0);
+                c0 += 2 * CLv;
+            }
+        }
+        if (e != hipSuccess || c0 == k) return e;
+        X += c0;
+        Y += c0;
+        k -= c0;
     }
     // widest column chunk that fits the registers without spilling
     const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
@@ -1661,18 +1929,14 @@ hipError_t spmm_t_impl(const DevMat &a, int k, const VT *dY, int64_t lddy, VT *d
         sp.dX = dX + c0;
         sp.lddx = (uint32_t)lddx;
         sp.alpha = alpha;
-        const dim3 block(64 * L.waves_per_wg);
+        typedef TransSink<VT, KC> TS;
         if (a.layout == 1)
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, 1>,
-                                       decode_kernel<1, VT, TransSink<VT, KC>, TransSink<VT, KC>::kOcc, 0>),
-                               dim3(L.grid), block, 0,
-                               st, a, sp);
-        else
-            hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), 1>,
-                                       decode_kernel<2, VT, TransSink<VT, KC>, occ_nnz(TransSink<VT, KC>::kOcc), 0>),
-                               dim3(L.grid), block, 0,
-                               st, a, sp);
-        return hipGetLastError();
+            return launch_persistent(pick_bd(a, decode_kernel<1, VT, TS, TS::kOcc, 1>,
+                                             decode_kernel<1, VT, TS, TS::kOcc, 0>),
+                                     a, L, st, a, sp);
+        return launch_persistent(pick_bd(a, decode_kernel<2, VT, TS, occ_nnz(TS::kOcc), 1>,
+                                         decode_kernel<2, VT, TS, occ_nnz(TS::kOcc), 0>),
+                                 a, L, st, a, sp);
     });
 }
 
@@ -1682,16 +1946,13 @@ hipError_t decode_impl(const DevMat &a, int32_t *col, void *vals, Launch L, hipS
     typename DecodeSink<VT>::Params sp;
     sp.col = col;
     sp.vals = (typename Bits<VT>::T *)vals;
-    const dim3 block(64 * L.waves_per_wg);
+    typedef DecodeSink<VT> DS;
     if (a.layout == 1)
-        hipLaunchKernelGGL(pick_bd(a, decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, 1>,
-                                   decode_kernel<1, VT, DecodeSink<VT>, DecodeSink<VT>::kOcc, 0>),
-                           dim3(L.grid), block, 0, st, a, sp);
-    else
-        hipLaunchKernelGGL(pick_bd(a, decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), 1>,
-                                   decode_kernel<2, VT, DecodeSink<VT>, occ_nnz(DecodeSink<VT>::kOcc), 0>),
-                           dim3(L.grid), block, 0, st, a, sp);
-    return hipGetLastError();
+        return launch_persistent(pick_bd(a, decode_kernel<1, VT, DS, DS::kOcc, 1>, decode_kernel<1, VT, DS, DS::kOcc, 0>),
+                                 a, L, st, a, sp);
+    return launch_persistent(pick_bd(a, decode_kernel<2, VT, DS, occ_nnz(DS::kOcc), 1>,
+                                     decode_kernel<2, VT, DS, occ_nnz(DS::kOcc), 0>),
+                             a, L, st, a, sp);
 }
 
 template <typename VT>

@@ -44,6 +44,8 @@ struct Launch {
     int ring_waves_per_wg = 16;  // ring kernels: wavefronts per workgroup
     int num_cus = 256;  // compute units of the device
     int wg_per_cu = 0;  // ring kernels: resident workgroups per CU (0: as many as fit)
+    int fixed_shape = 0;  // 1: waves_per_wg / grid as given; 0: the direct-read kernels pick
+                          // the workgroup size that keeps the most waves resident
 };
 
 // Columns of X/Y one SpMM launch takes at most (wider products run in
