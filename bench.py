@@ -79,24 +79,41 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, info):
-    """HBM bytes per launch of the decode kernel from the committed counter
-    summary (profiles/<workload>_traffic.txt), if it was taken on the current
-    kernel sources and the same encoded size; else None."""
-    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % workload)
+def profile_values(name, info):
+    """Key: value lines of the committed summary profiles/<name>.txt, if it was
+    taken on the current kernel sources and the same encoded size; else None."""
+    path = os.path.join(ROOT, "profiles", "%s.txt" % name)
     if not os.path.exists(path):
         return None
     kv = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
+            if ":" in line and not line.startswith("#") and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_hash") != kernel_source_hash():
         return None
     if int(kv.get("dtans_total_bytes", -1)) != info["total_bytes"]:
         return None
-    return int(kv["hbm_bytes_per_launch"])
+    return kv
+
+
+def measured_traffic(workload, info):
+    """HBM bytes per launch of the decode kernel from the committed counter
+    summary (profiles/<workload>_traffic.txt)."""
+    kv = profile_values("%s_traffic" % workload, info)
+    return None if kv is None else int(kv["hbm_bytes_per_launch"])
+
+
+def co_roofs(workload, info):
+    """Utilisation of the decode kernel's other units (VALU issue, the vector
+    memory address unit, LDS bandwidth) from the committed SQ/TA counter
+    summary (profiles/<workload>_decode_sq_counters.txt)."""
+    kv = profile_values("%s_decode_sq_counters" % workload, info)
+    if kv is None:
+        return None
+    return {k: float(kv[k]) for k in ("valu_busy", "ta_busy", "lds_bandwidth_frac", "waves_waiting_frac")
+            if k in kv} | {"source": "profiles/%s_decode_sq_counters.txt" % workload}
 
 
 def time_steps(torch, fn, steps, warmup):
@@ -313,6 +330,7 @@ def main():
         "encode_seconds": round(enc_s, 2),
     }
     res["roofline"]["traffic"] = measured_traffic(args.workload, info)
+    res["roofline"]["co_roofs"] = co_roofs(args.workload, info)
     if not args.no_csr:
         log("plain CSR baseline")
         B = P.CsrBaseline(rp, ci, v, n)
