@@ -279,8 +279,8 @@ def main():
                 B = P.Matrix.load(path)
                 B.set_launch(args.waves_per_wg, args.wg_per_cu, args.stream_stage)
                 mats.append(B)
-    for A in mats:
-        A.to_device()
+    for A in mats:  # upload and size each copy's scratch before any timing
+        A.to_device().reserve(k)
     gen = torch.Generator(device="cuda").manual_seed(2000 + W["cfg"])
     shape_x = (n,) if k == 1 else (n, k)
     shape_y = (m,) if k == 1 else (m, k)
@@ -414,8 +414,8 @@ def bench_autograd(args, torch, P):
                 path = os.path.join(td, "a.dtans")
                 M0.save(path)
                 mats += [P.Matrix.load(path) for _ in range(copies - 1)]
-        for M in mats:
-            M.to_device()
+        for M in mats:  # upload and size each copy's scratch before any timing
+            M.to_device().reserve(k)
         return mats
 
     mats, mats_t = replicate(A0), replicate(At0)

@@ -377,7 +377,9 @@ template <typename VT, int G, typename ACC = double>
 struct CoopSpmmSink {
     static constexpr bool kCoop = true;
     static constexpr int CL = 16 / (int)sizeof(VT), KC = G * CL, NG = kWave / G;
-    static constexpr int kOcc = 4;
+    // waves per SIMD to allow: with eight slots per lane the accumulators and
+    // the rows of X in flight do not fit beside the decoder in 128 registers
+    static constexpr int kOcc = G >= 8 ? 2 : 4;
     static_assert(G == 2 || G == 4 || G == 8, "2, 4 or 8 lanes per row of X");
     struct Params {
         const VT *X;
@@ -1210,9 +1212,12 @@ __device__ __forceinline__ void decode_sweep(const DevMat &a, const typename Sin
 }
 
 // MINW: waves per SIMD the register allocation must allow (8 lets two
-// 16-wave workgroups share a CU, which is what the LDS tables permit)
+// 16-wave workgroups share a CU, which is what the LDS tables permit).  Below
+// 4 the workgroup is capped at 4 * MINW waves, so that the compiler may give
+// a wave more than 128 registers.
+constexpr int decode_max_threads(int minw) { return minw >= 4 ? 1024 : 256 * minw; }
 template <int LAYOUT, typename VT, class Sink, int MINW, int TF>
-__global__ __launch_bounds__(1024, MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
+__global__ __launch_bounds__(decode_max_threads(MINW), MINW) void decode_kernel(DevMat a, typename Sink::Params sp) {
     __shared__ __align__(16) Tables<VT> tb;
     decode_sweep<LAYOUT, VT, Sink, TF>(a, sp, tb);
 }
@@ -1685,17 +1690,26 @@ struct Shape {
 };
 template <typename K>
 Shape fit_shape(K kern, const Launch &L) {
-    if (L.fixed_shape) return Shape{L.waves_per_wg, std::max(1, (L.grid + L.num_cus - 1) / L.num_cus)};
+    // the occupancy query does not know the kernel's workgroup-size bound, and
+    // a fixed shape may exceed it (kernels that need more than 128 registers)
+    auto max_threads = [&]() {
+        hipFuncAttributes fa;
+        return hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess ? fa.maxThreadsPerBlock : 1024;
+    };
+    if (L.fixed_shape)
+        return Shape{std::min(L.waves_per_wg, max_threads() / 64), std::max(1, (L.grid + L.num_cus - 1) / L.num_cus)};
     static std::mutex mu;
     static std::vector<std::pair<const void *, Shape>> cache;
     const void *key = (const void *)kern;
     std::lock_guard<std::mutex> lock(mu);
     for (const auto &c : cache)
         if (c.first == key) return c.second;
+    const int mt = max_threads();
     Shape best{L.waves_per_wg, std::max(1, (L.grid + L.num_cus - 1) / L.num_cus)};
     int best_res = 0;
     for (int w : {16, 12, 8, 4}) {
         int nb = 0;
+        if (64 * w > mt) continue;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * w, 0) != hipSuccess) continue;
         if (nb * w > best_res) {
             best_res = nb * w;
@@ -1832,7 +1846,7 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
     }
     // Several columns: groups of lanes share each row of X (CoopSpmmSink) when
     // its rows can be read as aligned 16-byte pieces at 32-bit byte offsets;
-    // chunks of 8 / 16 / 32 FP32 or 4 / 8 FP64 columns, the rest as below.
+    // chunks of 32 / 16 / 8 FP32 or 16 / 8 / 4 FP64 columns, the rest as below.
     const bool coop = (uintptr_t)X % 16 == 0 && (ldx * (int64_t)sizeof(VT)) % 16 == 0 &&
                       a.n * ldx * (int64_t)sizeof(VT) <= (1ll << 32);
     if (coop) {
@@ -1841,7 +1855,10 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         hipError_t e = hipSuccess;
         while (e == hipSuccess && k - c0 >= 2 * CLv) {
             const int left = k - c0;
-            if (left >= 4 * CLv) {
+            if (left >= 8 * CLv) {
+                e = launch(TypeBox<CoopSpmmSink<VT, 8>>(), 8 * CLv, c0);
+                c0 += 8 * CLv;
+            } else if (left >= 4 * CLv) {
                 e = launch(TypeBox<CoopSpmmSink<VT, 4>>(), 4 * CLv, c0);
                 c0 += 4 * CLv;
             } else {
@@ -1854,8 +1871,10 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         Y += c0;
         k -= c0;
     }
-    // widest column chunk that fits the registers without spilling
-    const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 1024;
+    // widest column chunk that fits the registers without spilling; FP32
+    // accumulators only while a lane's sum has at most 32 terms, so that the
+    // worst-case rounding error, (T - 1) 2^-24 |A||x|, stays below 2e-6 |A||x|
+    const bool f32acc = std::is_same<VT, float>::value && a.layout == 2 && a.lane_nnz <= 32;
     const int kcmax = std::is_same<VT, double>::value ? 8 : 16;
     return for_kc(k, kcmax, [&](auto KCc, int c0) {
         constexpr int KC = decltype(KCc)::value;
