@@ -210,6 +210,8 @@ def main():
                          "column - row + 2^29")
     ap.add_argument("--max-mult", type=int, default=0,
                     help="multiplicity cap of the alphabet fit (0: the library's 255; 256 is the paper's M)")
+    ap.add_argument("--escape-in-stream", action="store_true",
+                    help="escaped symbols inside the word stream instead of separate regions")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -260,7 +262,7 @@ def main():
     A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
                            waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu,
                            stream_stage=args.stream_stage, first_delta_column=args.first_delta_column,
-                           max_mult=args.max_mult)
+                           max_mult=args.max_mult, escape_in_stream=args.escape_in_stream)
     enc_s = time.perf_counter() - t0
     info = A0.info()
     log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
@@ -312,6 +314,7 @@ def main():
                    "stream_stage": {1: "direct", 2: "lds_ring"}[info["stream_stage"]],
                    "first_delta": "column" if info["first_delta_column"] else "column - row + 2^29",
                    "max_mult": args.max_mult or 255, "direct_table": bool(info["direct_table"]),
+                   "escapes": "in stream" if info["escape_in_stream"] else "separate regions",
                    "copies_rotated": copies},
         "compressed_GBps": round(achieved, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,

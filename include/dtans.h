@@ -88,6 +88,13 @@ typedef struct {
     int32_t first_delta_column; /* 1: the first delta of a row is its column (Sec. IV-A);
                               0: column - row + 2^29 (mod 2^32), which banded and
                               stencil matrices keep within the table */
+    int32_t escape_in_stream; /* where escaped symbols' raw bits go (Sec. IV-F): 0 = a
+                              separate region per wave; 1 = inside the word stream,
+                              read right after the decoding step that meets them (every
+                              step's word positions then depend on its escape count;
+                              SpMV/SpMM read such streams directly, never through the
+                              LDS ring; dtans_encode_csr only, the device encoders
+                              return DTANS_EUNSUPPORTED) */
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -109,7 +116,7 @@ typedef struct {
     int32_t stream_stage;                  /* SpMV word reads: 1 direct, 2 LDS ring */
     int32_t direct_table;                  /* 1: every base <= 255, used without correction */
     int32_t first_delta_column;            /* 1: first deltas are columns (the paper's form) */
-    int32_t reserved;
+    int32_t escape_in_stream;              /* 1: escapes inside the word stream */
 } dtans_info;
 
 typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */

@@ -13,7 +13,12 @@ Container layout (little endian), version 1:
   header (256 bytes): magic "CSRDTANS", u32 version=1, u32 dtype (1 FP32,
     2 FP64), u32 layout (1: lane = one row, 2: lane = T nonzeros), u32 T,
     i64 m, n, nnz, num_lanes, num_waves, n_words, n_esc_delta, n_esc_value,
-    u64 perm_seed, u64 FNV-1a-64 checksum of every byte after the header;
+    u64 perm_seed, u64 FNV-1a-64 checksum of every byte after the header,
+    u32 first-delta mode at byte 104, u32 escape mode at byte 108 (0: raw
+    bits of escaped symbols in the esc_delta / esc_value regions; 1: in the
+    word stream, a step's escaped deltas then values, (position, lane) order,
+    FP64 values as two words low first, between the words read before that
+    step and the words its checks read; Sec. IV-F);
   delta table, value table: 4096 entries of 16 bytes each
     (u64 symbol, u8 digit, u8 base-1, u8 flags: bit0 used, bit1 escape);
   row_ptr: (m+1) x i32;  word_off, esc_delta_off, esc_value_off:
@@ -70,6 +75,7 @@ class Container:
     escd: np.ndarray
     escv: np.ndarray
     first_mode: int = 0  # first delta of a row: 0 its column, 1 column - row + 2^29
+    esc_mode: int = 0    # escaped symbols: 0 separate regions, 1 in the word stream
 
 
 def _al8(x: int) -> int:
@@ -131,11 +137,13 @@ def read(path: str, verify: bool = True) -> Container:
     escv = take("<u8" if dtype == 2 else "<u4", nv)
     if o != len(data):
         raise ValueError("size mismatch")
-    (first_mode,) = struct.unpack_from("<I", data, 104)
+    (first_mode, esc_mode) = struct.unpack_from("<II", data, 104)
     if first_mode > 1:
         raise ValueError("bad first-delta mode")
+    if esc_mode > 1 or (esc_mode == 1 and (nd or nv)):
+        raise ValueError("bad escape mode")
     return Container(dtype, layout, T, m, n, nnz, lanes, waves, seed, dtab, vtab,
-                     row_ptr, woff, doff, voff, words, escd, escv, first_mode)
+                     row_ptr, woff, doff, voff, words, escd, escv, first_mode, esc_mode)
 
 
 def write(path: str, c: Container) -> None:
@@ -161,7 +169,7 @@ def write(path: str, c: Container) -> None:
     struct.pack_into("<qqqqqqqqQQ", hdr, 24, c.m, c.n, c.nnz, c.num_lanes, c.num_waves,
                      len(c.words), len(c.escd), len(c.escv), c.seed,
                      _fnv1a64_np(np.frombuffer(bytes(body), np.uint8)))
-    struct.pack_into("<I", hdr, 104, c.first_mode)
+    struct.pack_into("<II", hdr, 104, c.first_mode, c.esc_mode)
     with open(path, "wb") as f:
         f.write(bytes(hdr) + bytes(body))
 
@@ -251,7 +259,9 @@ def decode(c: Container):
                     s = c.dtab.symbol[slots[q][2 * pos]]
                     if s is None:
                         raise ValueError("unused slot")
-                    if s == ESC:
+                    if s == ESC and c.esc_mode == 1:
+                        s = nxt()
+                    elif s == ESC:
                         s = int(c.escd[dp]); dp += 1
                     g = lanes[q][0] + t
                     if t == 0 or g in first:
@@ -267,7 +277,11 @@ def decode(c: Container):
                     s = c.vtab.symbol[slots[q][2 * pos + 1]]
                     if s is None:
                         raise ValueError("unused slot")
-                    if s == ESC:
+                    if s == ESC and c.esc_mode == 1:
+                        s = nxt()
+                        if c.dtype == 2:
+                            s |= nxt() << 32
+                    elif s == ESC:
                         s = int(c.escv[vp]); vp += 1
                     keys[lanes[q][0] + t] = s
             for g in range(2):
@@ -331,7 +345,8 @@ def simple_tables(dkeys, vkeys, seed: int):
 
 
 def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int = 0,
-           tables: Optional[tuple] = None, seed: int = 1, first_mode: int = 0) -> Container:
+           tables: Optional[tuple] = None, seed: int = 1, first_mode: int = 0,
+           esc_mode: int = 0) -> Container:
     p = toy.CSR_DTANS
     row_ptr = np.asarray(row_ptr, np.int64)
     nnz = int(row_ptr[-1])
@@ -379,7 +394,29 @@ def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int 
                 if e is not None:
                     words.append(e[0][r])
         maxS = max(((cnt + 3) // 4 for _, cnt in lanes), default=0)
-        for j in range(maxS - 1):
+
+        def escapes(j, out_d, out_v):
+            for pos in range(4):
+                for g0, cnt in lanes:
+                    t = 4 * j + pos
+                    if t < cnt and dk[g0 + t] not in dset:
+                        out_d.append(dk[g0 + t])
+            for pos in range(4):
+                for g0, cnt in lanes:
+                    t = 4 * j + pos
+                    if t < cnt and vk[g0 + t] not in vset:
+                        if esc_mode == 1:  # one or two words, low first
+                            out_v.append(vk[g0 + t] & 0xFFFFFFFF)
+                            if dtype == 2:
+                                out_v.append(vk[g0 + t] >> 32)
+                        else:
+                            out_v.append(vk[g0 + t])
+
+        for j in range(maxS):
+            if esc_mode == 1:
+                escapes(j, words, words)
+            if j == maxS - 1:
+                break
             for k in range(3):
                 for e in per:
                     if e is None or j >= len(e[1]):
@@ -387,21 +424,14 @@ def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int 
                     x = e[1][j][k]
                     if x is not None:
                         words.append(x)
-        for j in range(maxS):
-            for pos in range(4):
-                for g0, cnt in lanes:
-                    t = 4 * j + pos
-                    if t < cnt and dk[g0 + t] not in dset:
-                        escd.append(dk[g0 + t])
-        for j in range(maxS):
-            for pos in range(4):
-                for g0, cnt in lanes:
-                    t = 4 * j + pos
-                    if t < cnt and vk[g0 + t] not in vset:
-                        escv.append(vk[g0 + t])
+        if esc_mode == 0:
+            for j in range(maxS):
+                escapes(j, escd, [])
+            for j in range(maxS):
+                escapes(j, [], escv)
         woff.append(len(words)); doff.append(len(escd)); voff.append(len(escv))
     return Container(dtype, layout, lane_nnz if layout == 2 else 0, m, n, nnz, len(ranges), waves,
                      seed, dtab, vtab, row_ptr.astype(np.int32), np.array(woff, np.uint64),
                      np.array(doff, np.uint64), np.array(voff, np.uint64),
                      np.array(words, np.uint32), np.array(escd, np.uint32),
-                     np.array(escv, np.uint64 if dtype == 2 else np.uint32), first_mode)
+                     np.array(escv, np.uint64 if dtype == 2 else np.uint32), first_mode, esc_mode)

@@ -19,16 +19,20 @@
  *     word streams (Sec. IV-B), tables of K = 4096 slots with multiplicity cap
  *     M = 256 (Sec. IV-C), decoding with W = 2^32, l = 8, o = 3, f = 2 one
  *     symbol at a time with a 128-bit state (Sec. IV-D, Alg. 3), the two-pass
- *     encoder (Sec. IV-E), escapes of rare symbols to a separate region, the
- *     end-of-row load skipping and tail padding, and slot permutation
- *     (Sec. IV-F).
+ *     encoder (Sec. IV-E), escapes of rare symbols (Sec. IV-F) either to a
+ *     separate region per wave or inside the word stream itself, read right
+ *     after the decoding step that met them, the end-of-row load skipping
+ *     and tail padding, and slot permutation (Sec. IV-F).
  *
  * Readings taken where the paper is silent (all listed in the design notes):
  * check g follows digit group g (symbols 1-4, then 5-8), digits are appended
  * as least significant, unpack takes w1 as most significant and i1 as the
  * lowest 12 bits, delta precedes value within a nonzero, escapes live in a
- * separate region per wave, and the last segment of a lane stream performs no
- * checks or loads.
+ * separate region per wave (or, in the in-stream mode, a step's escaped
+ * deltas and then its escaped values, each in (position, lane) order, sit in
+ * the word stream between the words read before the step and the words its
+ * checks read; an FP64 value takes two words, low half first), and the last
+ * segment of a lane stream performs no checks or loads.
  *
  * The multiplicity fit here is deliberately simple (proportional with a cap),
  * not the library's: any valid table decodes the same way.
@@ -301,6 +305,7 @@ typedef struct {
     int64_t m, n, nnz, num_lanes, num_waves, n_words, n_escd, n_escv;
     uint64_t seed;
     uint32_t first_mode; /* first delta of a row: 0 its column, 1 column - row + 2^29 */
+    uint32_t esc_mode;   /* escaped symbols: 0 separate regions, 1 in the word stream */
 } ohdr;
 
 /* First delta of a row (or of a lane starting inside a row), mode 1: the
@@ -482,10 +487,11 @@ static void write_table(uint8_t *b, const otable *t)
  */
 int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
                   const int32_t *row_ptr, const int32_t *col, const void *vals,
-                  int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode)
+                  int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode, int esc_mode)
 {
     if (m < 0 || n < 0 || nnz < 0 || (dtype != 1 && dtype != 2) ||
         (layout != 1 && layout != 2) || (first_mode != 0 && first_mode != 1) ||
+        (esc_mode != 0 && esc_mode != 1) ||
         (layout == 2 && (lane_nnz <= 0 || lane_nnz % 4 != 0)))
         return ORC_EINVAL;
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return ORC_EINVAL;
@@ -502,6 +508,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
     H.layout = (uint32_t)layout;
     H.lane_nnz = layout == 2 ? (uint32_t)lane_nnz : 0;
     H.m = m; H.n = n; H.nnz = nnz; H.seed = seed; H.first_mode = (uint32_t)first_mode;
+    H.esc_mode = (uint32_t)esc_mode;
     H.num_lanes = layout == 1 ? m : (nnz + lane_nnz - 1) / lane_nnz;
     H.num_waves = (H.num_lanes + OK_WAVE - 1) / OK_WAVE;
 
@@ -579,11 +586,31 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         }
         if (rc != ORC_OK) break;
         /* interleave: three initial rounds, then per step check 1, check 2,
-         * unconditional, each in lane order over the lanes still running */
+         * unconditional, each in lane order over the lanes still running;
+         * in the in-stream mode each step's escapes come first */
         for (int r = 0; r < 3; ++r)
             for (int q = 0; q < OK_WAVE; ++q)
                 if (lanes[q].S > 0) v64_push(&words, lanes[q].init[r]);
-        for (int64_t j = 0; j + 1 < maxS; ++j) {
+        for (int64_t j = 0; j < maxS; ++j) {
+            if (esc_mode == 1) {
+                for (int pos = 0; pos < 4; ++pos)
+                    for (int q = 0; q < OK_WAVE; ++q) {
+                        int64_t t = 4 * j + pos;
+                        if (t >= lane_c[q]) continue;
+                        int64_t g = lane_g0[q] + t;
+                        if (symbol_index(&td, dord, dkey[g]) == td.esc_index) v64_push(&words, dkey[g]);
+                    }
+                for (int pos = 0; pos < 4; ++pos)
+                    for (int q = 0; q < OK_WAVE; ++q) {
+                        int64_t t = 4 * j + pos;
+                        if (t >= lane_c[q]) continue;
+                        int64_t g = lane_g0[q] + t;
+                        if (symbol_index(&tv, vord, vkey[g]) != tv.esc_index) continue;
+                        v64_push(&words, vkey[g] & 0xffffffffu);
+                        if (dtype == 2) v64_push(&words, vkey[g] >> 32);
+                    }
+            }
+            if (j + 1 >= maxS) break;
             for (int q = 0; q < OK_WAVE; ++q)
                 if (j < lanes[q].S - 1 && lanes[q].load1[j]) v64_push(&words, lanes[q].w1[j]);
             for (int q = 0; q < OK_WAVE; ++q)
@@ -592,7 +619,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
                 if (j < lanes[q].S - 1) v64_push(&words, lanes[q].w3[j]);
         }
         /* escapes: per segment, per nonzero position, in lane order */
-        for (int64_t j = 0; j < maxS; ++j)
+        for (int64_t j = 0; j < maxS && esc_mode == 0; ++j)
             for (int pos = 0; pos < 4; ++pos)
                 for (int q = 0; q < OK_WAVE; ++q) {
                     int64_t t = 4 * j + pos;
@@ -600,7 +627,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
                     int64_t g = lane_g0[q] + t;
                     if (symbol_index(&td, dord, dkey[g]) == td.esc_index) v64_push(&escd, dkey[g]);
                 }
-        for (int64_t j = 0; j < maxS; ++j)
+        for (int64_t j = 0; j < maxS && esc_mode == 0; ++j)
             for (int pos = 0; pos < 4; ++pos)
                 for (int q = 0; q < OK_WAVE; ++q) {
                     int64_t t = 4 * j + pos;
@@ -664,6 +691,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         put_u64(buf + 80, (uint64_t)H.n_escv);
         put_u64(buf + 88, H.seed);
         put_u32(buf + 104, H.first_mode);
+        put_u32(buf + 108, H.esc_mode);
         put_u64(buf + 96, fnv1a64(buf + OK_HEADER, sz - OK_HEADER));
         FILE *fp = fopen(path, "wb");
         if (!fp || fwrite(buf, 1, sz, fp) != sz) rc = ORC_EIO;
@@ -722,6 +750,8 @@ static int read_file(const char *path, ofile *F)
     H->seed = get_u64(b + 88);
     H->first_mode = get_u32(b + 104);
     if (H->first_mode > 1) return ORC_ECORRUPT;
+    H->esc_mode = get_u32(b + 108);
+    if (H->esc_mode > 1 || (H->esc_mode == 1 && (H->n_escd != 0 || H->n_escv != 0))) return ORC_ECORRUPT;
     if (fnv1a64(b + OK_HEADER, F->size - OK_HEADER) != get_u64(b + 96)) return ORC_ECORRUPT;
     if ((H->dtype != 1 && H->dtype != 2) || (H->layout != 1 && H->layout != 2)) return ORC_ECORRUPT;
     if (H->m < 0 || H->n < 0 || H->nnz < 0 || H->n_words < 0 || H->n_escd < 0 || H->n_escv < 0)
@@ -837,7 +867,11 @@ int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void
                     if (j >= S[q] || t >= c[q]) continue;
                     int s = slot[q][2 * pos];
                     uint64_t delta;
-                    if (td.esc[s]) {
+                    if (td.esc[s] && H->esc_mode == 1) {
+                        uint32_t w32;
+                        NEXT_WORD(w32);
+                        delta = w32;
+                    } else if (td.esc[s]) {
                         if (dp >= dend) { rc = ORC_ECORRUPT; goto wave_done; }
                         delta = get_u32(F.escd_b + 4 * dp); ++dp;
                     } else {
@@ -858,7 +892,12 @@ int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void
                     if (j >= S[q] || t >= c[q]) continue;
                     int s = slot[q][2 * pos + 1];
                     uint64_t bits;
-                    if (tv.esc[s]) {
+                    if (tv.esc[s] && H->esc_mode == 1) {
+                        uint32_t lo, hi = 0;
+                        NEXT_WORD(lo);
+                        if (H->dtype == 2) NEXT_WORD(hi);
+                        bits = (uint64_t)hi << 32 | lo;
+                    } else if (tv.esc[s]) {
                         if (vp >= vend) { rc = ORC_ECORRUPT; goto wave_done; }
                         bits = H->dtype == 2 ? get_u64(F.escv_b + 8 * vp) : get_u32(F.escv_b + 4 * vp);
                         ++vp;
@@ -899,8 +938,9 @@ int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void
     return rc;
 }
 
-/* header fields: out[0..12] = dtype, layout, lane_nnz, m, n, nnz, num_lanes,
- * num_waves, n_words, n_escd, n_escv, seed, file size */
+/* header fields: out[0..14] = dtype, layout, lane_nnz, m, n, nnz, num_lanes,
+ * num_waves, n_words, n_escd, n_escv, seed, file size, first-delta mode,
+ * escape mode */
 int oracle_read_header(const char *path, int64_t *out)
 {
     ofile F;
@@ -910,7 +950,7 @@ int oracle_read_header(const char *path, int64_t *out)
         out[3] = F.H.m; out[4] = F.H.n; out[5] = F.H.nnz;
         out[6] = F.H.num_lanes; out[7] = F.H.num_waves; out[8] = F.H.n_words;
         out[9] = F.H.n_escd; out[10] = F.H.n_escv; out[11] = (int64_t)F.H.seed;
-        out[12] = (int64_t)F.size; out[13] = F.H.first_mode;
+        out[12] = (int64_t)F.size; out[13] = F.H.first_mode; out[14] = F.H.esc_mode;
     }
     free(F.buf);
     return rc;

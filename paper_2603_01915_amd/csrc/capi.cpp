@@ -176,9 +176,10 @@ void nonempty_rows(const Container &c, std::vector<int32_t> &lane_row, std::vect
 // SpMV stages its streams through an LDS ring only when asked to (measured:
 // the direct-read kernels, at twice the waves per SIMD, are faster on the
 // workloads here); a wavefront's run of streams is addressed with 32-bit
-// offsets.
+// offsets.  Streams with escapes inside them are read directly: a step may
+// read more of such a stream than the ring keeps ahead of it.
 bool uses_ring(const dtans_matrix *h) {
-    return h->stage == DTANS_STAGE_RING && 4 * (int64_t)h->c.words.size() < (1ll << 31);
+    return h->stage == DTANS_STAGE_RING && h->c.esc_mode == 0 && 4 * (int64_t)h->c.words.size() < (1ll << 31);
 }
 
 // Default workgroup shape of the decode kernels: LDS admits 160 KiB /
@@ -300,6 +301,7 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.base_direct = direct ? 1 : 0;
     v.no_escape = c.dtab.has_escape || c.vtab.has_escape ? 0 : 1;
     v.first_mode = c.first_mode;
+    v.esc_in_stream = c.esc_mode == 1 ? 1 : 0;
     h->device = dev;
     h->num_cus = device_cus(dev);
     h->uploaded = true;
@@ -583,6 +585,8 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
         return set_err(DTANS_EINVAL, "stream_stage must be 0, 1 or 2");
     if (o.max_mult < 0 || o.max_mult > kMaxBase)
         return set_err(DTANS_EINVAL, "max_mult must be 0..256");
+    if (o.escape_in_stream != 0 && o.escape_in_stream != 1)
+        return set_err(DTANS_EINVAL, "escape_in_stream must be 0 or 1");
     const size_t vb = dtype == DTANS_F64 ? 8 : 4;
     std::vector<int32_t> scol;
     std::vector<uint8_t> sval;
@@ -610,6 +614,7 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
     p.seed = o.perm_seed;
     p.max_mult = o.max_mult ? (uint32_t)o.max_mult : 255u;
     p.first_mode = o.first_delta_column ? 0u : 1u;
+    p.esc_mode = o.escape_in_stream ? 1u : 0u;
     int layout = 0, T = 0;
     auto_encoding(m, nnz, row_ptr, o, dtype == DTANS_F64, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
@@ -750,6 +755,7 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->bits_per_nnz = c.nnz ? 8.0 * o->stream_bytes / c.nnz : 0.0;
     o->stream_stage = uses_ring(mat) ? DTANS_STAGE_RING : DTANS_STAGE_DIRECT;
     o->first_delta_column = c.first_mode == 0;
+    o->escape_in_stream = c.esc_mode == 1;
     o->direct_table = 1;
     for (int i = 0; i < kSlots; ++i)
         if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))

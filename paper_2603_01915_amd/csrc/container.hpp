@@ -30,6 +30,11 @@ struct Table {
 struct Container {
     uint32_t dtype = kF64, layout = kLayoutRow, lane_nnz = 0;
     uint32_t first_mode = 0;  // first delta of a row: 0 its column, 1 relative to the row
+    // escaped symbols (Sec. IV-F): 0 in separate regions per wave (escd, escv);
+    // 1 in the word stream, a decoding step's escaped deltas and then values
+    // ((position, lane) order; FP64 values as two words, low first) between
+    // the words read before that step and the words its checks read
+    uint32_t esc_mode = 0;
     int64_t m = 0, n = 0, nnz = 0, num_lanes = 0, num_waves = 0;
     uint64_t seed = 1;
     Table dtab, vtab;
@@ -69,6 +74,7 @@ struct EncodeParams {
     uint32_t lane_nnz = 0;
     uint32_t max_mult = 255;  // multiplicity cap, at most M = 256
     uint32_t first_mode = 1;  // Container::first_mode
+    uint32_t esc_mode = 0;    // Container::esc_mode
     uint64_t seed = 1;
     int threads = 0;  // 0 = hardware concurrency
 };

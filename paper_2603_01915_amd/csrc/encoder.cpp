@@ -384,6 +384,7 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     if (p.layout != kLayoutRow && p.layout != kLayoutNnz) return fail("EINVAL", "bad layout");
     if (p.layout == kLayoutNnz && (p.lane_nnz == 0 || p.lane_nnz % 4 != 0 || p.lane_nnz > (1u << 24)))
         return fail("EINVAL", "lane_nnz must be a positive multiple of 4");
+    if (p.esc_mode > 1) return fail("EINVAL", "escape mode must be 0 (separate) or 1 (in stream)");
     if (!row_ptr || (nnz > 0 && (!col || !vals))) return fail("EINVAL", "null array");
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail("EINVAL", "row_ptr must run from 0 to nnz");
     const int threads = thread_count(p.threads);
@@ -432,6 +433,7 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     c.nnz = nnz;
     c.seed = p.seed;
     c.first_mode = p.first_mode;
+    c.esc_mode = p.esc_mode;
     c.row_ptr.assign(row_ptr, row_ptr + m + 1);
     c.num_lanes = p.layout == kLayoutRow ? m : (nnz + p.lane_nnz - 1) / p.lane_nnz;
     c.num_waves = (c.num_lanes + kWave - 1) / kWave;
@@ -484,6 +486,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     table_stats(vfit, nnz, c.vtab);
     const int dpad = pad_symbol(c.dtab, dsm), vpad = pad_symbol(c.vtab, vsm);
     if (dev) {
+        if (c.esc_mode != 0)
+            return fail("EUNSUPPORTED", "the device encoder writes escapes to separate regions only");
         AlphabetMap da, va;
         auto fill = [](const SlotMap &sm, int pad, AlphabetMap &a) {
             a.hkey = sm.hkey;
@@ -551,7 +555,25 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
             for (int k = 0; k < 3; ++k)
                 for (int q = 0; q < kWave; ++q)
                     if (lanes[q].S > 0) o.words.push_back(lanes[q].init[k]);
-            for (int64_t j = 0; j + 1 < maxS; ++j) {
+            const bool in_stream = c.esc_mode == 1;
+            for (int64_t j = 0; j < maxS; ++j) {
+                if (in_stream) {  // step j's escapes, read right after its table lookups
+                    for (int k = 0; k < 4; ++k)
+                        for (int q = 0; q < kWave; ++q) {
+                            int64_t t = 4 * j + k;
+                            if (t < cnts[q] && dsym[g0s[q] + t] == dsm.esc_index)
+                                o.words.push_back((uint32_t)dkey[g0s[q] + t]);
+                        }
+                    for (int k = 0; k < 4; ++k)
+                        for (int q = 0; q < kWave; ++q) {
+                            int64_t t = 4 * j + k;
+                            if (t < cnts[q] && vsym[g0s[q] + t] == vsm.esc_index) {
+                                o.words.push_back((uint32_t)vkey[g0s[q] + t]);
+                                if (c.dtype == kF64) o.words.push_back((uint32_t)(vkey[g0s[q] + t] >> 32));
+                            }
+                        }
+                }
+                if (j + 1 >= maxS) break;
                 for (int q = 0; q < kWave; ++q)
                     if (j < lanes[q].S - 1 && lanes[q].load[2 * j]) o.words.push_back(lanes[q].w[3 * j]);
                 for (int q = 0; q < kWave; ++q)
@@ -560,14 +582,14 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
                 for (int q = 0; q < kWave; ++q)
                     if (j < lanes[q].S - 1) o.words.push_back(lanes[q].w[3 * j + 2]);
             }
-            for (int64_t j = 0; j < maxS; ++j)
+            for (int64_t j = 0; j < maxS && !in_stream; ++j)
                 for (int k = 0; k < 4; ++k)
                     for (int q = 0; q < kWave; ++q) {
                         int64_t t = 4 * j + k;
                         if (t < cnts[q] && dsym[g0s[q] + t] == dsm.esc_index)
                             o.escd.push_back((uint32_t)dkey[g0s[q] + t]);
                     }
-            for (int64_t j = 0; j < maxS; ++j)
+            for (int64_t j = 0; j < maxS && !in_stream; ++j)
                 for (int k = 0; k < 4; ++k)
                     for (int q = 0; q < kWave; ++q) {
                         int64_t t = 4 * j + k;
@@ -686,6 +708,7 @@ std::string save_container(const Container &c, const std::string &path) {
     memcpy(&b[24], h64, 64);
     memcpy(&b[88], &c.seed, 8);
     memcpy(&b[104], &c.first_mode, 4);
+    memcpy(&b[108], &c.esc_mode, 4);
     uint64_t chk = fnv1a(b.data() + kHeader, sz - kHeader);
     memcpy(&b[96], &chk, 8);
     FILE *f = fopen(path.c_str(), "wb");
@@ -725,8 +748,10 @@ std::string load_container(const std::string &path, Container &c) {
     const int64_t nw = h64[5], nd = h64[6], nv = h64[7];
     memcpy(&c.seed, &b[88], 8);
     memcpy(&c.first_mode, &b[104], 4);
+    memcpy(&c.esc_mode, &b[108], 4);
     if (c.dtype != kF32 && c.dtype != kF64) return fail("ECORRUPT", "bad dtype");
     if (c.first_mode > 1) return fail("ECORRUPT", "bad first-delta mode");
+    if (c.esc_mode > 1 || (c.esc_mode == 1 && (nd != 0 || nv != 0))) return fail("ECORRUPT", "bad escape mode");
     if (c.layout != kLayoutRow && c.layout != kLayoutNnz) return fail("ECORRUPT", "bad layout");
     if (c.m < 0 || c.n < 0 || c.nnz < 0 || nw < 0 || nd < 0 || nv < 0 || c.m >= (1ll << 31) ||
         c.n >= (1ll << 31) || c.nnz >= (1ll << 31))
@@ -849,7 +874,10 @@ std::string host_decode(const Container &c, int32_t *colout, uint64_t *valout) {
                         if (j >= S[q] || t >= cnt[q]) continue;
                         uint64_t e = dm[sl[q][2 * k]];
                         uint32_t delta = (uint32_t)e & (kDeltaLimit - 1);
-                        if ((uint32_t)e >> 31) {
+                        if ((uint32_t)e >> 31 && c.esc_mode == 1) {
+                            if (wp >= wend) { err("stream overrun"); break; }
+                            delta = c.words[wp++];
+                        } else if ((uint32_t)e >> 31) {
                             if (dp >= dend) { err("escape overrun"); break; }
                             delta = c.escd[dp++];
                         }
@@ -871,7 +899,12 @@ std::string host_decode(const Container &c, int32_t *colout, uint64_t *valout) {
                         if (j >= S[q] || t >= cnt[q]) continue;
                         int s = sl[q][2 * k + 1];
                         uint64_t bits = c.vtab.sym[s];
-                        if ((dm[s] >> 30) & 1) {
+                        if ((dm[s] >> 30) & 1 && c.esc_mode == 1) {
+                            const int nwv = c.dtype == kF64 ? 2 : 1;
+                            if (wp + nwv > wend) { err("stream overrun"); break; }
+                            bits = c.words[wp++];
+                            if (nwv == 2) bits |= (uint64_t)c.words[wp++] << 32;
+                        } else if ((dm[s] >> 30) & 1) {
                             if (vp >= vend) { err("escape overrun"); break; }
                             bits = c.escv[vp++];
                         }

@@ -378,8 +378,10 @@ struct CoopSpmmSink {
     static constexpr bool kCoop = true;
     static constexpr int CL = 16 / (int)sizeof(VT), KC = G * CL, NG = kWave / G;
     // waves per SIMD to allow: with eight slots per lane the accumulators and
-    // the rows of X in flight do not fit beside the decoder in 128 registers
-    static constexpr int kOcc = G >= 8 ? 2 : 4;
+    // the rows of X in flight do not fit beside the decoder in 128 registers;
+    // with two or four, 168 registers avoid spills (measured faster than four
+    // waves per SIMD with spills, and than two)
+    static constexpr int kOcc = G >= 8 ? 2 : 3;
     static_assert(G == 2 || G == 4 || G == 8, "2, 4 or 8 lanes per row of X");
     struct Params {
         const VT *X;
@@ -683,6 +685,12 @@ struct GlobalWords {
         const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
         return *(const uint32_t *)(W + (p + 4 * lane));
     }
+    // the word at byte offset pos (uniform) + off (per lane): escapes stored
+    // in the stream
+    __device__ __forceinline__ uint32_t word_at(uint32_t pos, uint32_t off) const {
+        const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
+        return *(const uint32_t *)(W + (p + off));
+    }
     // Nothing in the memory system fetches a stream ahead of its reads, so
     // every step's words would come from HBM.  Once the first words are
     // requested, one load per lane touches the next 64 cache lines (128 B)
@@ -771,6 +779,12 @@ struct RingWords {
     __device__ __forceinline__ uint32_t read_lanes(uint32_t pos, uint32_t ln) const {
         const uint32_t *at = ring + (((pos + skew) >> 2) & (kRing - 1));
         return at[ln];
+    }
+    // from memory (streams with escapes inside are never staged through a
+    // ring: a step may read more of them than the ring holds ahead)
+    __device__ __forceinline__ uint32_t word_at(uint32_t pos, uint32_t off) const {
+        const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
+        return *(const uint32_t *)(base + (p + skew + off));
     }
     __device__ __forceinline__ uint32_t prefetch(uint32_t, uint32_t) const { return 0u; }
     __device__ __forceinline__ void retire(uint32_t) const {}
@@ -947,19 +961,48 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
         if constexpr (TF != 2) {
             const uint32_t fl = md[0] | md[1] | md[2] | md[3] | mv[0] | mv[1] | mv[2] | mv[3];
             if ((FULL ? ~0ull : ballot(act)) & ballot((int32_t)fl < 0)) {  // uniform
+                if (a.esc_in_stream) {
+                    // raw bits in the word stream at the read position:
+                    // deltas, then values (FP64 as two words, low first),
+                    // each nonzero position in lane order; the step's own
+                    // words follow them
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool f = act && k < rem && (int32_t)md[k] < 0;
-                    const uint64_t mk = ballot(f);
-                    if (f) dl[k] = ED[dpos + lane_prefix(mk)] * scale;
-                    dpos += (uint32_t)__popcll(mk);
-                }
+                    for (int k = 0; k < 4; ++k) {
+                        const bool f = act && k < rem && (int32_t)md[k] < 0;
+                        const uint64_t mk = ballot(f);
+                        if (f) dl[k] = src.word_at(pos, 4 * lane_prefix(mk)) * scale;
+                        pos += 4 * (uint32_t)__popcll(mk);
+                    }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool f = act && k < rem && (int32_t)mv[k] < 0;
-                    const uint64_t mk = ballot(f);
-                    if (f) v[k] = EV[vpos + lane_prefix(mk)];
-                    vpos += (uint32_t)__popcll(mk);
+                    for (int k = 0; k < 4; ++k) {
+                        const bool f = act && k < rem && (int32_t)mv[k] < 0;
+                        const uint64_t mk = ballot(f);
+                        if (f) {
+                            const uint32_t o = (uint32_t)sizeof(VT) * lane_prefix(mk);
+                            if constexpr (sizeof(VT) == 8) {
+                                const uint64_t bits = (uint64_t)src.word_at(pos, o + 4) << 32 | src.word_at(pos, o);
+                                v[k] = __builtin_bit_cast(VT, bits);
+                            } else {
+                                v[k] = __builtin_bit_cast(VT, src.word_at(pos, o));
+                            }
+                        }
+                        pos += (uint32_t)sizeof(VT) * (uint32_t)__popcll(mk);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const bool f = act && k < rem && (int32_t)md[k] < 0;
+                        const uint64_t mk = ballot(f);
+                        if (f) dl[k] = ED[dpos + lane_prefix(mk)] * scale;
+                        dpos += (uint32_t)__popcll(mk);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const bool f = act && k < rem && (int32_t)mv[k] < 0;
+                        const uint64_t mk = ballot(f);
+                        if (f) v[k] = EV[vpos + lane_prefix(mk)];
+                        vpos += (uint32_t)__popcll(mk);
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {

@@ -35,6 +35,7 @@ struct DevMat {
     int32_t base_direct;       // 1: table metadata holds bases, not bases - 1
     int32_t no_escape;         // 1: neither table holds the escape symbol
     uint32_t first_mode;       // first delta of a row: 0 its column, 1 relative to the row
+    int32_t esc_in_stream;     // 1: escaped symbols sit in the word stream (else escd / escv)
 };
 
 struct Launch {

@@ -9,7 +9,7 @@
 
 int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                   const int32_t *col, const void *vals, int dtype, int layout, int lane_nnz,
-                  uint64_t seed, int first_mode);
+                  uint64_t seed, int first_mode, int esc_mode);
 int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void *vals_out);
 
 static uint64_t state = 99;
@@ -22,7 +22,7 @@ static uint64_t rnd(void) /* xorshift64 (Marsaglia) */
 }
 
 static int one(const char *path, int64_t m, int64_t n, int maxlen, int pool, int dtype, int layout,
-               int T, int first)
+               int T, int first, int esc)
 {
     int32_t *rp = malloc((m + 1) * sizeof(int32_t));
     int64_t cap = m * (int64_t)maxlen + 1;
@@ -46,7 +46,7 @@ static int one(const char *path, int64_t m, int64_t n, int maxlen, int pool, int
         rp[i + 1] = (int32_t)nnz;
     }
     const void *vals = dtype == 2 ? (const void *)v : (const void *)f;
-    int bad = oracle_encode(path, m, n, nnz, rp, ci, vals, dtype, layout, T, rnd(), first);
+    int bad = oracle_encode(path, m, n, nnz, rp, ci, vals, dtype, layout, T, rnd(), first, esc);
     int32_t *rp2 = malloc((m + 1) * sizeof(int32_t));
     int32_t *ci2 = malloc((nnz + 1) * sizeof(int32_t));
     double *v2 = malloc((nnz + 1) * sizeof(double));
@@ -55,7 +55,8 @@ static int one(const char *path, int64_t m, int64_t n, int maxlen, int pool, int
         bad = memcmp(rp, rp2, (m + 1) * sizeof(int32_t)) != 0 || memcmp(ci, ci2, nnz * sizeof(int32_t)) != 0 ||
               memcmp(vals, v2, nnz * (dtype == 2 ? 8 : 4)) != 0;
     }
-    if (bad) printf("failure: m=%lld dtype=%d layout=%d T=%d first=%d\n", (long long)m, dtype, layout, T, first);
+    if (bad)
+        printf("failure: m=%lld dtype=%d layout=%d T=%d first=%d esc=%d\n", (long long)m, dtype, layout, T, first, esc);
     free(rp); free(ci); free(v); free(f); free(pv); free(rp2); free(ci2); free(v2);
     return bad != 0;
 }
@@ -66,12 +67,13 @@ int main(int argc, char **argv)
     int fails = 0, cases = 0;
     for (int dtype = 1; dtype <= 2; ++dtype)
         for (int layout = 1; layout <= 2; ++layout)
-            for (int first = 0; first <= 1; ++first) {
-                fails += one(path, 150, 300, 18, 30, dtype, layout, layout == 2 ? 12 : 0, first);
-                fails += one(path, 97, 5000, 40, 700, dtype, layout, layout == 2 ? 32 : 0, first);
-                fails += one(path, 3, 7, 2, 1, dtype, layout, layout == 2 ? 4 : 0, first);
-                cases += 3;
-            }
+            for (int first = 0; first <= 1; ++first)
+                for (int esc = 0; esc <= 1; ++esc) {
+                    fails += one(path, 150, 300, 18, 30, dtype, layout, layout == 2 ? 12 : 0, first, esc);
+                    fails += one(path, 97, 5000, 40, 700, dtype, layout, layout == 2 ? 32 : 0, first, esc);
+                    fails += one(path, 3, 7, 2, 1, dtype, layout, layout == 2 ? 4 : 0, first, esc);
+                    cases += 3;
+                }
     printf("%d cases, %d failures\n", cases, fails);
     return fails != 0;
 }
