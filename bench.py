@@ -61,6 +61,9 @@ def make_workload(name):
     if name == "rmat":
         rp, ci, v = workloads.rmat(22)
         return dict(name="rmat scale22 ef16 fp32 spmv", rp=rp, ci=ci, v=v, n=1 << 22, k=1, cfg=3)
+    if name == "skewed":
+        rp, ci, v = workloads.skewed_rows()
+        return dict(name="skewed rows 2^21 fp64 spmv", rp=rp, ci=ci, v=v, n=1 << 21, k=1, cfg=6)
     if name.startswith("pruned"):
         k = int(name[len("pruned"):] or 1)
         rp, ci, v = workloads.pruned_weight()
@@ -212,6 +215,8 @@ def main():
                     help="multiplicity cap of the alphabet fit (0: the library's 255; 256 is the paper's M)")
     ap.add_argument("--escape-in-stream", action="store_true",
                     help="escaped symbols inside the word stream instead of separate regions")
+    ap.add_argument("--sort-window", type=int, default=0,
+                    help="row layout: encode rows sorted by length within windows of this many rows")
     ap.add_argument("--copies", type=int, default=0, help="0: enough to exceed twice the MALL")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -262,7 +267,8 @@ def main():
     A0 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
                            waves_per_wg=args.waves_per_wg, wg_per_cu=args.wg_per_cu,
                            stream_stage=args.stream_stage, first_delta_column=args.first_delta_column,
-                           max_mult=args.max_mult, escape_in_stream=args.escape_in_stream)
+                           max_mult=args.max_mult, escape_in_stream=args.escape_in_stream,
+                           sort_window=args.sort_window)
     enc_s = time.perf_counter() - t0
     info = A0.info()
     log("encoded in %.1f s: %.2f bits/nnz, %d bytes (CSR %d)" % (enc_s, info["bits_per_nnz"],
@@ -315,6 +321,7 @@ def main():
                    "first_delta": "column" if info["first_delta_column"] else "column - row + 2^29",
                    "max_mult": args.max_mult or 255, "direct_table": bool(info["direct_table"]),
                    "escapes": "in stream" if info["escape_in_stream"] else "separate regions",
+                   "sort_window": info["sort_window"],
                    "copies_rotated": copies},
         "compressed_GBps": round(achieved, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,

@@ -95,6 +95,16 @@ typedef struct {
                               SpMV/SpMM read such streams directly, never through the
                               LDS ring; dtans_encode_csr only, the device encoders
                               return DTANS_EUNSUPPORTED) */
+    int32_t sort_window;   /* ROW layout: 0 = rows in CSR order; a multiple of 64 = a
+                              SELL-C-sigma base (Sec. VII's other starting formats;
+                              Kreutzer et al. 2014): within each window of that many
+                              rows, rows are encoded by descending length (ties in
+                              order), so a wave's 64 lanes get rows of similar
+                              length; the order is stored and every product and
+                              dtans_decode_csr work in the original row order.
+                              dtans_encode_csr only; batches and dtans_spmv_sym
+                              return DTANS_EUNSUPPORTED for such matrices */
+    int32_t reserved0;
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;
 
@@ -117,6 +127,8 @@ typedef struct {
     int32_t direct_table;                  /* 1: every base <= 255, used without correction */
     int32_t first_delta_column;            /* 1: first deltas are columns (the paper's form) */
     int32_t escape_in_stream;              /* 1: escapes inside the word stream */
+    int32_t sort_window;                   /* rows sorted within windows of this many (0: none) */
+    int32_t reserved;
 } dtans_info;
 
 typedef struct dtans_matrix dtans_matrix; /* owns its host container and device copy */

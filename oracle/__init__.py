@@ -56,7 +56,8 @@ def lib():
         L.oracle_csr_spmtv_f64.argtypes = [I64, I64, P, P, P, P, P, D, D]
         L.oracle_csr_spmm_f64.argtypes = [I64, I64, P, P, P, P, I64, P, I64, D, D]
         L.oracle_encode.argtypes = [ctypes.c_char_p, I64, I64, I64, P, P, P, ctypes.c_int,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int]
         L.oracle_encode.restype = ctypes.c_int
         L.oracle_decode.argtypes = [ctypes.c_char_p, P, P, P]
         L.oracle_decode.restype = ctypes.c_int
@@ -120,29 +121,32 @@ def spmm(row_ptr, col, val, X, Y=None, alpha=1.0, beta=0.0):
 
 
 def encode(path: str, m: int, n: int, row_ptr, col, vals, layout: int = 1, lane_nnz: int = 0,
-           seed: int = 1, first_mode: int = 0, esc_mode: int = 0) -> None:
+           seed: int = 1, first_mode: int = 0, esc_mode: int = 0, sigma: int = 0) -> None:
     """Write a CSR-dtANS container with the reference encoder.  first_mode 0:
     the first delta of a row is its column (the paper's form); 1: column -
     row + 2^29 modulo 2^32 (the library's default).  esc_mode 0: escaped
     symbols in separate regions per wave; 1: in the word stream, after the
-    words read before the step that decodes them (Sec. IV-F)."""
+    words read before the step that decodes them (Sec. IV-F).  sigma (row
+    layout, a multiple of 64): rows sorted by descending length within
+    windows of sigma rows before encoding, the order stored (a SELL-C-sigma
+    base, Sec. VII); decoding restores the original order."""
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col, np.int32)
     vals = np.ascontiguousarray(vals)
     dtype = {np.dtype(np.float32): 1, np.dtype(np.float64): 2}[vals.dtype]
     rc = lib().oracle_encode(path.encode(), m, n, int(rp[-1]), _p(rp), _p(ci), _p(vals), dtype,
-                             layout, lane_nnz, seed, first_mode, esc_mode)
+                             layout, lane_nnz, seed, first_mode, esc_mode, sigma)
     if rc:
         raise OracleError("oracle_encode: " + ERRORS.get(rc, str(rc)))
 
 
 def read_header(path: str) -> dict:
-    out = np.zeros(15, np.int64)
+    out = np.zeros(16, np.int64)
     rc = lib().oracle_read_header(path.encode(), _p(out))
     if rc:
         raise OracleError("oracle_read_header: " + ERRORS.get(rc, str(rc)))
     keys = ["dtype", "layout", "lane_nnz", "m", "n", "nnz", "num_lanes", "num_waves", "n_words",
-            "n_esc_delta", "n_esc_value", "seed", "file_bytes", "first_mode", "esc_mode"]
+            "n_esc_delta", "n_esc_value", "seed", "file_bytes", "first_mode", "esc_mode", "sigma"]
     return dict(zip(keys, (int(v) for v in out)))
 
 

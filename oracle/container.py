@@ -18,7 +18,11 @@ Container layout (little endian), version 1:
     bits of escaped symbols in the esc_delta / esc_value regions; 1: in the
     word stream, a step's escaped deltas then values, (position, lane) order,
     FP64 values as two words low first, between the words read before that
-    step and the words its checks read; Sec. IV-F);
+    step and the words its checks read; Sec. IV-F), u32 row-sort window sigma
+    at byte 112 (0: rows in CSR order; else the encoded rows are the original
+    ones sorted by descending length within windows of sigma rows, a
+    SELL-C-sigma base, and an (m) x i32 section after esc_value holds the
+    original row of every encoded row);
   delta table, value table: 4096 entries of 16 bytes each
     (u64 symbol, u8 digit, u8 base-1, u8 flags: bit0 used, bit1 escape);
   row_ptr: (m+1) x i32;  word_off, esc_delta_off, esc_value_off:
@@ -76,6 +80,8 @@ class Container:
     escv: np.ndarray
     first_mode: int = 0  # first delta of a row: 0 its column, 1 column - row + 2^29
     esc_mode: int = 0    # escaped symbols: 0 separate regions, 1 in the word stream
+    sigma: int = 0       # row-sort window (0: CSR order)
+    perm: Optional[np.ndarray] = None  # original row of each encoded row (sigma > 0)
 
 
 def _al8(x: int) -> int:
@@ -135,15 +141,18 @@ def read(path: str, verify: bool = True) -> Container:
     words = take("<u4", nw)
     escd = take("<u4", nd)
     escv = take("<u8" if dtype == 2 else "<u4", nv)
+    (first_mode, esc_mode, sigma) = struct.unpack_from("<III", data, 104)
+    perm = take("<i4", m) if sigma else None
     if o != len(data):
         raise ValueError("size mismatch")
-    (first_mode, esc_mode) = struct.unpack_from("<II", data, 104)
+    if sigma % WAVE or (sigma and layout != 1):
+        raise ValueError("bad row-sort window")
     if first_mode > 1:
         raise ValueError("bad first-delta mode")
     if esc_mode > 1 or (esc_mode == 1 and (nd or nv)):
         raise ValueError("bad escape mode")
     return Container(dtype, layout, T, m, n, nnz, lanes, waves, seed, dtab, vtab,
-                     row_ptr, woff, doff, voff, words, escd, escv, first_mode, esc_mode)
+                     row_ptr, woff, doff, voff, words, escd, escv, first_mode, esc_mode, sigma, perm)
 
 
 def write(path: str, c: Container) -> None:
@@ -163,13 +172,15 @@ def write(path: str, c: Container) -> None:
     put(np.asarray(c.words, "<u4").tobytes())
     put(np.asarray(c.escd, "<u4").tobytes())
     put(np.asarray(c.escv, "<u8" if c.dtype == 2 else "<u4").tobytes())
+    if c.sigma:
+        put(np.asarray(c.perm, "<i4").tobytes())
     hdr = bytearray(HEADER)
     hdr[:8] = b"CSRDTANS"
     struct.pack_into("<IIII", hdr, 8, 1, c.dtype, c.layout, c.lane_nnz)
     struct.pack_into("<qqqqqqqqQQ", hdr, 24, c.m, c.n, c.nnz, c.num_lanes, c.num_waves,
                      len(c.words), len(c.escd), len(c.escv), c.seed,
                      _fnv1a64_np(np.frombuffer(bytes(body), np.uint8)))
-    struct.pack_into("<II", hdr, 104, c.first_mode, c.esc_mode)
+    struct.pack_into("<III", hdr, 104, c.first_mode, c.esc_mode, c.sigma)
     with open(path, "wb") as f:
         f.write(bytes(hdr) + bytes(body))
 
@@ -307,7 +318,33 @@ def decode(c: Container):
             raise ValueError("wave %d: stored and consumed words differ" % w)
     vdt = np.uint64 if c.dtype == 2 else np.uint32
     vals = np.array(keys, dtype=vdt).view(np.float64 if c.dtype == 2 else np.float32)
-    return c.row_ptr.copy(), col.astype(np.int32), vals
+    if not c.sigma:
+        return c.row_ptr.copy(), col.astype(np.int32), vals
+    # rows back into their original order; the stored order must be the
+    # canonical one for these row lengths
+    lens = np.diff(c.row_ptr.astype(np.int64))
+    orig_len = np.zeros(c.m, np.int64)
+    orig_len[c.perm] = lens
+    if sorted(c.perm.tolist()) != list(range(c.m)) or list(sigma_order(orig_len, c.sigma)) != c.perm.tolist():
+        raise ValueError("bad row order")
+    rp = np.zeros(c.m + 1, np.int64)
+    rp[1:] = np.cumsum(orig_len)
+    col2, vals2 = np.zeros_like(col), np.zeros_like(vals)
+    for r in range(c.m):
+        i = int(c.perm[r])
+        col2[rp[i]:rp[i + 1]] = col[c.row_ptr[r]:c.row_ptr[r + 1]]
+        vals2[rp[i]:rp[i + 1]] = vals[c.row_ptr[r]:c.row_ptr[r + 1]]
+    return rp.astype(np.int32), col2.astype(np.int32), vals2
+
+
+def sigma_order(lengths, sigma: int) -> List[int]:
+    """SELL-C-sigma row order (Kreutzer et al. 2014): within each window of
+    sigma rows, rows by descending length, ties in their original order."""
+    m = len(lengths)
+    out = []
+    for w0 in range(0, m, sigma):
+        out.extend(sorted(range(w0, min(m, w0 + sigma)), key=lambda i: -int(lengths[i])))
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -346,9 +383,19 @@ def simple_tables(dkeys, vkeys, seed: int):
 
 def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int = 0,
            tables: Optional[tuple] = None, seed: int = 1, first_mode: int = 0,
-           esc_mode: int = 0) -> Container:
+           esc_mode: int = 0, sigma: int = 0) -> Container:
     p = toy.CSR_DTANS
     row_ptr = np.asarray(row_ptr, np.int64)
+    perm = None
+    if sigma:  # encode the rows in SELL-C-sigma order
+        assert layout == 1 and sigma % WAVE == 0
+        perm = np.array(sigma_order(np.diff(row_ptr), sigma), np.int32)
+        col = np.asarray(col)
+        vals = np.asarray(vals)
+        rows = [np.arange(row_ptr[i], row_ptr[i + 1]) for i in perm]
+        idx = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+        col, vals = col[idx], vals[idx]
+        row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
     nnz = int(row_ptr[-1])
     ranges = lane_ranges(layout, lane_nnz, m, nnz, row_ptr)
     dk = delta_keys(row_ptr, col, ranges, first_mode)
@@ -434,4 +481,5 @@ def encode(m, n, row_ptr, col, vals, dtype: int, layout: int = 1, lane_nnz: int 
                      seed, dtab, vtab, row_ptr.astype(np.int32), np.array(woff, np.uint64),
                      np.array(doff, np.uint64), np.array(voff, np.uint64),
                      np.array(words, np.uint32), np.array(escd, np.uint32),
-                     np.array(escv, np.uint64 if dtype == 2 else np.uint32), first_mode, esc_mode)
+                     np.array(escv, np.uint64 if dtype == 2 else np.uint32), first_mode, esc_mode,
+                     sigma, perm)

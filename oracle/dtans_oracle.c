@@ -306,6 +306,7 @@ typedef struct {
     uint64_t seed;
     uint32_t first_mode; /* first delta of a row: 0 its column, 1 column - row + 2^29 */
     uint32_t esc_mode;   /* escaped symbols: 0 separate regions, 1 in the word stream */
+    uint32_t sigma;      /* 0: rows in their order; else rows sorted within windows of sigma */
 } ohdr;
 
 /* First delta of a row (or of a lane starting inside a row), mode 1: the
@@ -485,9 +486,10 @@ static void write_table(uint8_t *b, const otable *t)
  * dtype 2: vals are double.  layout 1: one row per lane; layout 2: lane_nnz
  * (multiple of 4) nonzeros per lane.  Columns must be sorted within rows.
  */
-int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
-                  const int32_t *row_ptr, const int32_t *col, const void *vals,
-                  int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode, int esc_mode)
+static int encode_rows(const char *path, int64_t m, int64_t n, int64_t nnz,
+                       const int32_t *row_ptr, const int32_t *col, const void *vals,
+                       int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode, int esc_mode,
+                       uint32_t sigma, const int32_t *perm)
 {
     if (m < 0 || n < 0 || nnz < 0 || (dtype != 1 && dtype != 2) ||
         (layout != 1 && layout != 2) || (first_mode != 0 && first_mode != 1) ||
@@ -509,6 +511,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
     H.lane_nnz = layout == 2 ? (uint32_t)lane_nnz : 0;
     H.m = m; H.n = n; H.nnz = nnz; H.seed = seed; H.first_mode = (uint32_t)first_mode;
     H.esc_mode = (uint32_t)esc_mode;
+    H.sigma = sigma;
     H.num_lanes = layout == 1 ? m : (nnz + lane_nnz - 1) / lane_nnz;
     H.num_waves = (H.num_lanes + OK_WAVE - 1) / OK_WAVE;
 
@@ -655,6 +658,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         sz = align8(sz + 4 * (size_t)H.n_words);
         sz = align8(sz + 4 * (size_t)H.n_escd);
         sz = align8(sz + vsz * (size_t)H.n_escv);
+        if (sigma) sz = align8(sz + 4 * (size_t)m);
         uint8_t *buf = (uint8_t *)calloc(sz, 1);
         size_t o = OK_HEADER;
         write_table(buf + o, &td); o = align8(o + 16 * OK_SLOTS);
@@ -675,6 +679,10 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
             else put_u32(buf + o + 4 * i, (uint32_t)escv.p[i]);
         }
         o = align8(o + vsz * (size_t)H.n_escv);
+        if (sigma) {
+            for (int64_t i = 0; i < m; ++i) put_u32(buf + o + 4 * i, (uint32_t)perm[i]);
+            o = align8(o + 4 * (size_t)m);
+        }
         /* header */
         memcpy(buf, "CSRDTANS", 8);
         put_u32(buf + 8, 1);
@@ -692,6 +700,7 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
         put_u64(buf + 88, H.seed);
         put_u32(buf + 104, H.first_mode);
         put_u32(buf + 108, H.esc_mode);
+        put_u32(buf + 112, H.sigma);
         put_u64(buf + 96, fnv1a64(buf + OK_HEADER, sz - OK_HEADER));
         FILE *fp = fopen(path, "wb");
         if (!fp || fwrite(buf, 1, sz, fp) != sz) rc = ORC_EIO;
@@ -706,6 +715,73 @@ int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
     return rc;
 }
 
+/*
+ * Row order of a SELL-C-sigma base (Kreutzer et al., SIAM J. Sci. Comput.
+ * 2014), the paper's suggested starting point other than CSR (Sec. VII):
+ * within each window of sigma consecutive rows, rows by descending number of
+ * nonzeros, ties in their original order; perm[r] = original row of encoded
+ * row r.  The encoded matrix is the row-permuted one; a wave (C = 64 lanes)
+ * then holds rows of similar lengths.  sigma = 0 keeps the CSR order.
+ */
+static void sigma_order(int64_t m, const int32_t *row_ptr, uint32_t sigma, int32_t *perm)
+{
+    for (int64_t i = 0; i < m; ++i) perm[i] = (int32_t)i;
+    if (!sigma) return;
+    for (int64_t w0 = 0; w0 < m; w0 += sigma) {
+        int64_t w1 = w0 + (int64_t)sigma < m ? w0 + (int64_t)sigma : m;
+        /* insertion sort: stable, plain */
+        for (int64_t i = w0 + 1; i < w1; ++i) {
+            int32_t r = perm[i];
+            int32_t len = row_ptr[r + 1] - row_ptr[r];
+            int64_t j = i;
+            while (j > w0 && row_ptr[perm[j - 1] + 1] - row_ptr[perm[j - 1]] < len) {
+                perm[j] = perm[j - 1];
+                --j;
+            }
+            perm[j] = r;
+        }
+    }
+}
+
+/*
+ * Encode a CSR matrix into a container file.  dtype 1: vals are float,
+ * dtype 2: vals are double.  layout 1: one row per lane; layout 2: lane_nnz
+ * (multiple of 4) nonzeros per lane.  Columns must be sorted within rows.
+ * esc_mode: 0 escapes in separate regions, 1 in the word stream.  sigma:
+ * 0, or (layout 1 only, a multiple of 64) the window of the row sort above.
+ */
+int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz,
+                  const int32_t *row_ptr, const int32_t *col, const void *vals,
+                  int dtype, int layout, int lane_nnz, uint64_t seed, int first_mode, int esc_mode,
+                  int sigma)
+{
+    if (sigma == 0)
+        return encode_rows(path, m, n, nnz, row_ptr, col, vals, dtype, layout, lane_nnz, seed, first_mode,
+                           esc_mode, 0, NULL);
+    if (sigma < 0 || sigma % OK_WAVE || layout != 1 || m < 0 || nnz < 0 || (dtype != 1 && dtype != 2) ||
+        row_ptr[0] != 0 || row_ptr[m] != nnz)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < m; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return ORC_EINVAL;
+    size_t vsz = dtype == 2 ? 8 : 4;
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *rp2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t *c2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    uint8_t *v2 = (uint8_t *)malloc(vsz * (size_t)(nnz > 0 ? nnz : 1));
+    sigma_order(m, row_ptr, (uint32_t)sigma, perm);
+    rp2[0] = 0;
+    for (int64_t r = 0; r < m; ++r) {
+        int32_t i = perm[r], len = row_ptr[i + 1] - row_ptr[i];
+        memcpy(c2 + rp2[r], col + row_ptr[i], sizeof(int32_t) * (size_t)len);
+        memcpy(v2 + vsz * (size_t)rp2[r], (const uint8_t *)vals + vsz * (size_t)row_ptr[i], vsz * (size_t)len);
+        rp2[r + 1] = rp2[r] + len;
+    }
+    int rc = encode_rows(path, m, n, nnz, rp2, c2, v2, dtype, layout, lane_nnz, seed, first_mode, esc_mode,
+                         (uint32_t)sigma, perm);
+    free(perm); free(rp2); free(c2); free(v2);
+    return rc;
+}
+
 /* ======================================================================
  * decoder (Alg. 3, one lane after another in 64-lane lockstep)
  * ====================================================================== */
@@ -717,7 +793,7 @@ typedef struct {
     const uint8_t *dtab, *vtab;
     const int32_t *row_ptr;
     const uint64_t *woff, *doff, *voff; /* may be unaligned: read via get_u64 */
-    const uint8_t *woff_b, *doff_b, *voff_b, *words_b, *escd_b, *escv_b;
+    const uint8_t *woff_b, *doff_b, *voff_b, *words_b, *escd_b, *escv_b, *perm_b;
 } ofile;
 
 static int read_file(const char *path, ofile *F)
@@ -752,6 +828,8 @@ static int read_file(const char *path, ofile *F)
     if (H->first_mode > 1) return ORC_ECORRUPT;
     H->esc_mode = get_u32(b + 108);
     if (H->esc_mode > 1 || (H->esc_mode == 1 && (H->n_escd != 0 || H->n_escv != 0))) return ORC_ECORRUPT;
+    H->sigma = get_u32(b + 112);
+    if (H->sigma % OK_WAVE || (H->sigma && H->layout != 1)) return ORC_ECORRUPT;
     if (fnv1a64(b + OK_HEADER, F->size - OK_HEADER) != get_u64(b + 96)) return ORC_ECORRUPT;
     if ((H->dtype != 1 && H->dtype != 2) || (H->layout != 1 && H->layout != 2)) return ORC_ECORRUPT;
     if (H->m < 0 || H->n < 0 || H->nnz < 0 || H->n_words < 0 || H->n_escd < 0 || H->n_escv < 0)
@@ -766,6 +844,7 @@ static int read_file(const char *path, ofile *F)
     need = align8(need + 4 * (size_t)H->n_words);
     need = align8(need + 4 * (size_t)H->n_escd);
     need = align8(need + vsz * (size_t)H->n_escv);
+    if (H->sigma) need = align8(need + 4 * (size_t)H->m);
     if (need != F->size) return ORC_ECORRUPT;
     F->dtab = b + o; o = align8(o + 16 * OK_SLOTS);
     F->vtab = b + o; o = align8(o + 16 * OK_SLOTS);
@@ -775,7 +854,8 @@ static int read_file(const char *path, ofile *F)
     F->voff_b = b + o; o = align8(o + 8 * (size_t)(H->num_waves + 1));
     F->words_b = b + o; o = align8(o + 4 * (size_t)H->n_words);
     F->escd_b = b + o; o = align8(o + 4 * (size_t)H->n_escd);
-    F->escv_b = b + o;
+    F->escv_b = b + o; o = align8(o + vsz * (size_t)H->n_escv);
+    F->perm_b = H->sigma ? b + o : NULL;
     /* geometry */
     int64_t lanes = H->layout == 1 ? H->m
                                    : (H->lane_nnz ? (H->nnz + H->lane_nnz - 1) / H->lane_nnz : -1);
@@ -810,8 +890,48 @@ static int read_table(const uint8_t *b, dtable *t, int is_delta)
 }
 
 /*
+ * Rows of a sigma-sorted container back into their original order (in place
+ * on the decoder's outputs).  The stored order must be the one sigma_order
+ * gives for the decoded row lengths.
+ */
+static int unpermute_rows(const ohdr *H, const uint8_t *perm_b, int32_t *row_ptr, int32_t *col, void *vals)
+{
+    int64_t m = H->m, nnz = H->nnz;
+    size_t vsz = H->dtype == 2 ? 8 : 4;
+    size_t mm = (size_t)(m > 0 ? m : 1), nn = (size_t)(nnz > 0 ? nnz : 1);
+    int32_t *perm = (int32_t *)malloc(4 * mm), *chk = (int32_t *)malloc(4 * mm);
+    int32_t *rp = (int32_t *)malloc(4 * (size_t)(m + 1)), *c = (int32_t *)malloc(4 * nn);
+    uint8_t *v = (uint8_t *)malloc(vsz * nn), *seen = (uint8_t *)calloc(mm, 1);
+    int rc = ORC_OK;
+    for (int64_t r = 0; r < m && rc == ORC_OK; ++r) {
+        int64_t i = (int32_t)get_u32(perm_b + 4 * r);
+        if (i < 0 || i >= m || seen[i] || i / H->sigma != r / H->sigma) rc = ORC_ECORRUPT;
+        else { seen[i] = 1; perm[r] = (int32_t)i; }
+    }
+    if (rc == ORC_OK) {
+        for (int64_t r = 0; r < m; ++r) rp[perm[r] + 1] = row_ptr[r + 1] - row_ptr[r];
+        rp[0] = 0;
+        for (int64_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
+        sigma_order(m, rp, H->sigma, chk);
+        if (m > 0 && memcmp(chk, perm, 4 * (size_t)m) != 0) rc = ORC_ECORRUPT;
+    }
+    if (rc == ORC_OK) {
+        for (int64_t r = 0; r < m; ++r) {
+            int32_t i = perm[r], len = row_ptr[r + 1] - row_ptr[r];
+            memcpy(c + rp[i], col + row_ptr[r], 4 * (size_t)len);
+            memcpy(v + vsz * (size_t)rp[i], (const uint8_t *)vals + vsz * (size_t)row_ptr[r], vsz * (size_t)len);
+        }
+        memcpy(row_ptr, rp, 4 * (size_t)(m + 1));
+        memcpy(col, c, 4 * (size_t)nnz);
+        memcpy(vals, v, vsz * (size_t)nnz);
+    }
+    free(perm); free(chk); free(rp); free(c); free(v); free(seen);
+    return rc;
+}
+
+/*
  * Decode a container into CSR arrays (row_ptr: m+1, col: nnz, vals: nnz of
- * the container's dtype).  Returns 0 or an error code; any inconsistency
+ * the container's dtype), rows in their original order.  Returns 0 or an error code; any inconsistency
  * between the words a decoder consumes and the words stored is an error.
  */
 int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void *vals_out)
@@ -933,14 +1053,15 @@ int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void
     wave_done:;
 #undef NEXT_WORD
     }
+    if (rc == ORC_OK && H->sigma) rc = unpermute_rows(H, F.perm_b, row_ptr_out, col_out, vals_out);
     free(first);
     free(F.buf);
     return rc;
 }
 
-/* header fields: out[0..14] = dtype, layout, lane_nnz, m, n, nnz, num_lanes,
+/* header fields: out[0..15] = dtype, layout, lane_nnz, m, n, nnz, num_lanes,
  * num_waves, n_words, n_escd, n_escv, seed, file size, first-delta mode,
- * escape mode */
+ * escape mode, row-sort window */
 int oracle_read_header(const char *path, int64_t *out)
 {
     ofile F;
@@ -951,6 +1072,7 @@ int oracle_read_header(const char *path, int64_t *out)
         out[6] = F.H.num_lanes; out[7] = F.H.num_waves; out[8] = F.H.n_words;
         out[9] = F.H.n_escd; out[10] = F.H.n_escv; out[11] = (int64_t)F.H.seed;
         out[12] = (int64_t)F.size; out[13] = F.H.first_mode; out[14] = F.H.esc_mode;
+        out[15] = F.H.sigma;
     }
     free(F.buf);
     return rc;

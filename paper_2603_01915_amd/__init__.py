@@ -84,7 +84,7 @@ def _ld(t) -> int:
 
 
 def _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, stream_stage, max_mult,
-                 first_delta_column, escape_in_stream=False) -> EncodeOpts:
+                 first_delta_column, escape_in_stream=False, sort_window=0) -> EncodeOpts:
     o = EncodeOpts()
     L.dtans_default_opts(ctypes.byref(o))
     o.layout = _LAYOUTS[layout]
@@ -97,6 +97,7 @@ def _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, 
     o.max_mult = max_mult
     o.first_delta_column = int(bool(first_delta_column))
     o.escape_in_stream = int(bool(escape_in_stream))
+    o.sort_window = int(sort_window)
     return o
 
 
@@ -137,12 +138,15 @@ class Matrix:
                  waves_per_wg: int = 0, wg_per_cu: int = 0, sort_rows: bool = False,
                  seed: int = 1, stream_stage: int = 0, max_mult: int = 0,
                  first_delta_column: bool = False, gpu_encode: bool = False,
-                 escape_in_stream: bool = False, stream=None) -> "Matrix":
+                 escape_in_stream: bool = False, sort_window: int = 0, stream=None) -> "Matrix":
         """Encode host CSR arrays.  ``gpu_encode`` runs every pass over the
         nonzeros (keys, histograms, symbols, words, escapes) on the current
         GPU; the container is the same as the host encoder's.
         ``escape_in_stream`` puts the raw bits of escaped symbols into the
-        word stream instead of separate regions (host encoder only)."""
+        word stream instead of separate regions (host encoder only).
+        ``sort_window`` (row layout, a multiple of 64) encodes the rows sorted
+        by descending length within windows of that many rows (a SELL-C-sigma
+        base); products and ``decode_csr`` keep the original row order."""
         L = _lib.load()
         rp = _np(row_ptr, np.int32)
         ci = _np(col, np.int32)
@@ -151,7 +155,7 @@ class Matrix:
             v = v.astype(np.float64)
         m, nnz = len(rp) - 1, len(ci)
         o = _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, sort_rows, seed, stream_stage,
-                         max_mult, first_delta_column, escape_in_stream)
+                         max_mult, first_delta_column, escape_in_stream, sort_window)
         h = ctypes.c_void_p()
         if gpu_encode:
             _lib.check(L.dtans_encode_csr_gpu(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(v),

@@ -33,7 +33,8 @@ class EncodeOpts(ctypes.Structure):
                 ("waves_per_wg", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
                 ("sort_rows", ctypes.c_int32), ("stream_stage", ctypes.c_int32),
                 ("max_mult", ctypes.c_int32), ("first_delta_column", ctypes.c_int32),
-                ("escape_in_stream", ctypes.c_int32), ("perm_seed", ctypes.c_uint64)]
+                ("escape_in_stream", ctypes.c_int32), ("sort_window", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("perm_seed", ctypes.c_uint64)]
 
 
 class Info(ctypes.Structure):
@@ -51,7 +52,8 @@ class Info(ctypes.Structure):
                 ("delta_cross_entropy", ctypes.c_double),
                 ("value_cross_entropy", ctypes.c_double), ("bits_per_nnz", ctypes.c_double),
                 ("stream_stage", ctypes.c_int32), ("direct_table", ctypes.c_int32),
-                ("first_delta_column", ctypes.c_int32), ("escape_in_stream", ctypes.c_int32)]
+                ("first_delta_column", ctypes.c_int32), ("escape_in_stream", ctypes.c_int32),
+                ("sort_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -105,6 +105,7 @@ struct dtans_matrix {
     int waves_per_wg = 0, wg_per_cu = 0, stage = 0;
     DevMat view{};
     std::vector<uint32_t> escv32;  // FP32 escaped values as uploaded (kept with the handle)
+    std::vector<int32_t> orig_row_ptr;  // row-sorted containers: the original matrix's row pointers
     // device scratch of the products (layout NNZ partial sums, the transposed
     // product's per-CU copies of dX); sized by dtans_to_device / dtans_reserve
     void *scratch = nullptr;
@@ -250,7 +251,8 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
         escv_src = h->escv32.data();
         escv_bytes = h->escv32.size() * 4;
     }
-    void *p[16];
+    void *p[18];
+    if (c.sigma && !original_row_ptr(c, h->orig_row_ptr)) return set_err(DTANS_ECORRUPT, "bad row order");
     HIP_TRY(h->bufs.upload(&p[0], h->gtab.data(), 8 * h->gtab.size(), st));
     HIP_TRY(h->bufs.upload(&p[1], h->gval.data(), h->gval.size(), st));
     HIP_TRY(h->bufs.upload(&p[2], c.row_ptr.data(), 4 * c.row_ptr.size(), st));
@@ -267,6 +269,11 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     HIP_TRY(h->bufs.upload(&p[13], h->nzr.data(), 4 * h->nzr.size(), st));
     HIP_TRY(h->bufs.upload(&p[14], h->empty_rows.data(), 4 * h->empty_rows.size(), st));
     HIP_TRY(h->bufs.upload(&p[15], h->split_long.data(), 4 * h->split_long.size(), st));
+    p[16] = p[17] = nullptr;
+    if (c.sigma) {
+        HIP_TRY(h->bufs.upload(&p[16], c.perm.data(), 4 * c.perm.size(), st));
+        HIP_TRY(h->bufs.upload(&p[17], h->orig_row_ptr.data(), 4 * h->orig_row_ptr.size(), st));
+    }
     // the copies complete before the call returns, so that products on any
     // stream find the matrix in place (the one synchronisation of a handle)
     HIP_TRY(hipStreamSynchronize(st));
@@ -302,6 +309,8 @@ dtans_status upload(dtans_matrix *h, hipStream_t st) {
     v.no_escape = c.dtab.has_escape || c.vtab.has_escape ? 0 : 1;
     v.first_mode = c.first_mode;
     v.esc_in_stream = c.esc_mode == 1 ? 1 : 0;
+    v.row_perm = c.sigma ? (const int32_t *)p[16] : nullptr;
+    v.orig_row_ptr = c.sigma ? (const int32_t *)p[17] : nullptr;
     h->device = dev;
     h->num_cus = device_cus(dev);
     h->uploaded = true;
@@ -496,6 +505,7 @@ dtans_status tune_candidates(int64_t m, int64_t nnz, const int32_t *row_ptr, dta
             dtans_encode_opts c = o;
             c.layout = e.first;
             c.lane_nnz = e.second;
+            if (c.layout == DTANS_LAYOUT_NNZ) c.sort_window = 0;  // row sorting is a ROW-layout option
             c.waves_per_wg = w;
             c.wg_per_cu = g;
             c.stream_stage = stage;
@@ -587,6 +597,8 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
         return set_err(DTANS_EINVAL, "max_mult must be 0..256");
     if (o.escape_in_stream != 0 && o.escape_in_stream != 1)
         return set_err(DTANS_EINVAL, "escape_in_stream must be 0 or 1");
+    if (o.sort_window < 0 || o.sort_window % 64)
+        return set_err(DTANS_EINVAL, "sort_window must be 0 or a positive multiple of 64");
     const size_t vb = dtype == DTANS_F64 ? 8 : 4;
     std::vector<int32_t> scol;
     std::vector<uint8_t> sval;
@@ -615,6 +627,8 @@ dtans_status encode_common(int64_t m, int64_t n, int64_t nnz, const int32_t *row
     p.max_mult = o.max_mult ? (uint32_t)o.max_mult : 255u;
     p.first_mode = o.first_delta_column ? 0u : 1u;
     p.esc_mode = o.escape_in_stream ? 1u : 0u;
+    p.sigma = (uint32_t)o.sort_window;
+    if (o.sort_window && o.layout == DTANS_LAYOUT_AUTO) o.layout = DTANS_LAYOUT_ROW;
     int layout = 0, T = 0;
     auto_encoding(m, nnz, row_ptr, o, dtype == DTANS_F64, layout, T);
     p.layout = layout == DTANS_LAYOUT_NNZ ? kLayoutNnz : kLayoutRow;
@@ -756,6 +770,7 @@ dtans_status dtans_matrix_info(const dtans_matrix *mat, dtans_info *o) {
     o->stream_stage = uses_ring(mat) ? DTANS_STAGE_RING : DTANS_STAGE_DIRECT;
     o->first_delta_column = c.first_mode == 0;
     o->escape_in_stream = c.esc_mode == 1;
+    o->sort_window = (int32_t)c.sigma;
     o->direct_table = 1;
     for (int i = 0; i < kSlots; ++i)
         if (((c.dtab.flags[i] & 1) && c.dtab.base[i] > 255) || ((c.vtab.flags[i] & 1) && c.vtab.base[i] > 255))
@@ -841,6 +856,7 @@ dtans_status dtans_spmv_sym(dtans_matrix *mat, const void *diag, const void *x, 
     if (s) return s;
     const Container &c = mat->c;
     if (c.m != c.n) return set_err(DTANS_EINVAL, "the triangle of a symmetric matrix must be square");
+    if (c.sigma) return set_err(DTANS_EUNSUPPORTED, "the symmetric product needs rows in CSR order");
     if (c.m > 0 && (!x || !y)) return set_err(DTANS_EINVAL, "null vector");
     if (x == y && c.m > 0) return set_err(DTANS_EINVAL, "y must not alias x");
     // y = alpha S x + beta y, then y += alpha d .* x, then y += alpha S^T x
@@ -860,7 +876,8 @@ dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_
     if (s) return s;
     const Container &c = mat->c;
     if (!row_ptr || (c.nnz > 0 && (!col_idx || !vals))) return set_err(DTANS_EINVAL, "null output");
-    HIP_TRY(hipMemcpyAsync(row_ptr, mat->view.row_ptr, 4 * (size_t)(c.m + 1),
+    // the original matrix (row-sorted containers decode into its positions)
+    HIP_TRY(hipMemcpyAsync(row_ptr, c.sigma ? mat->view.orig_row_ptr : mat->view.row_ptr, 4 * (size_t)(c.m + 1),
                            hipMemcpyDeviceToDevice, st));
     hipError_t e = launch_decode(mat->view, c.dtype == kF64, col_idx, vals, plan_launch(mat), st);
     if (e != hipSuccess) return hip_err(e, "dtans_decode_csr launch");
@@ -884,6 +901,8 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
         if ((mats[i]->c.dtype == kF64) != f64) return set_err(DTANS_EINVAL, "batch matrices must share a dtype");
         if (mats[i]->c.layout != kLayoutRow)
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must use the ROW layout");
+        if (mats[i]->c.sigma)
+            return set_err(DTANS_EUNSUPPORTED, "batch matrices must keep their rows in CSR order");
         if (mats[i]->c.n * (int64_t)mats[i]->c.value_bytes() > (1ll << 32))
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must have x of at most 4 GiB");
         dtans_status s = reserve(mats[i], 1, nullptr);

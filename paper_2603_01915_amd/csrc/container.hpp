@@ -4,6 +4,7 @@
 
 #include <stdint.h>
 
+#include <algorithm>
 #include <array>
 #include <string>
 #include <vector>
@@ -35,6 +36,12 @@ struct Container {
     // ((position, lane) order; FP64 values as two words, low first) between
     // the words read before that step and the words its checks read
     uint32_t esc_mode = 0;
+    // row order (layout ROW): 0 = CSR order; else the encoded rows are the
+    // original ones sorted by descending length within windows of sigma rows
+    // (a SELL-C-sigma base, C = 64) and perm[r] is the original row of
+    // encoded row r; row_ptr is then the encoded matrix's
+    uint32_t sigma = 0;
+    std::vector<int32_t> perm;
     int64_t m = 0, n = 0, nnz = 0, num_lanes = 0, num_waves = 0;
     uint64_t seed = 1;
     Table dtab, vtab;
@@ -59,6 +66,36 @@ struct Container {
 };
 
 // the (nonempty) row holding nonzero g: the last i with row_ptr[i] <= g
+// SELL-C-sigma row order (Kreutzer et al. 2014): within each window of sigma
+// rows, rows by descending number of nonzeros, ties in their original order;
+// perm[r] = original row placed at r.
+inline void sigma_order(int64_t m, const int32_t *row_ptr, uint32_t sigma, std::vector<int32_t> &perm) {
+    perm.resize(m);
+    for (int64_t i = 0; i < m; ++i) perm[i] = (int32_t)i;
+    if (!sigma) return;
+    for (int64_t w = 0; w < m; w += sigma) {
+        auto b = perm.begin() + w, e = perm.begin() + std::min<int64_t>(m, w + sigma);
+        std::stable_sort(b, e, [&](int32_t x, int32_t y) {
+            return row_ptr[x + 1] - row_ptr[x] > row_ptr[y + 1] - row_ptr[y];
+        });
+    }
+}
+
+// Row pointers of the original matrix of a row-sorted container; false when
+// perm is not a permutation of the rows.
+inline bool original_row_ptr(const Container &c, std::vector<int32_t> &orp) {
+    orp.assign(c.m + 1, 0);
+    std::vector<uint8_t> seen(c.m, 0);
+    for (int64_t r = 0; r < c.m; ++r) {
+        const int32_t i = c.perm[r];
+        if (i < 0 || i >= c.m || seen[i]) return false;
+        seen[i] = 1;
+        orp[i + 1] = c.row_ptr[r + 1] - c.row_ptr[r];
+    }
+    for (int64_t i = 0; i < c.m; ++i) orp[i + 1] += orp[i];
+    return true;
+}
+
 inline int64_t row_of(const std::vector<int32_t> &row_ptr, int64_t g) {
     int64_t lo = 0, hi = (int64_t)row_ptr.size() - 1;  // row_ptr[lo] <= g < row_ptr[hi]
     while (hi - lo > 1) {
@@ -75,6 +112,7 @@ struct EncodeParams {
     uint32_t max_mult = 255;  // multiplicity cap, at most M = 256
     uint32_t first_mode = 1;  // Container::first_mode
     uint32_t esc_mode = 0;    // Container::esc_mode
+    uint32_t sigma = 0;       // Container::sigma (layout ROW, a multiple of 64)
     uint64_t seed = 1;
     int threads = 0;  // 0 = hardware concurrency
 };

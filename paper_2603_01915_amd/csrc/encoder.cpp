@@ -387,6 +387,32 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
     if (p.esc_mode > 1) return fail("EINVAL", "escape mode must be 0 (separate) or 1 (in stream)");
     if (!row_ptr || (nnz > 0 && (!col || !vals))) return fail("EINVAL", "null array");
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail("EINVAL", "row_ptr must run from 0 to nnz");
+    if (p.sigma) {
+        // sorted rows: encode the row-permuted matrix, keep the order
+        if (p.layout != kLayoutRow || p.sigma % kWave)
+            return fail("EINVAL", "a row-sort window needs the ROW layout and a multiple of 64 rows");
+        if (dev) return fail("EUNSUPPORTED", "the device encoder keeps rows in CSR order");
+        for (int64_t i = 0; i < m; ++i)
+            if (row_ptr[i + 1] < row_ptr[i]) return fail("EINVAL", "row_ptr decreases at row " + std::to_string(i));
+        std::vector<int32_t> perm, rp2(m + 1), c2(nnz);
+        sigma_order(m, row_ptr, p.sigma, perm);
+        const size_t vb = dtype == kF64 ? 8 : 4;
+        std::vector<uint8_t> v2(vb * (size_t)nnz);
+        rp2[0] = 0;
+        for (int64_t r = 0; r < m; ++r) {
+            const int32_t i = perm[r], len = row_ptr[i + 1] - row_ptr[i];
+            std::copy(col + row_ptr[i], col + row_ptr[i] + len, c2.begin() + rp2[r]);
+            memcpy(&v2[vb * (size_t)rp2[r]], (const uint8_t *)vals + vb * (size_t)row_ptr[i], vb * (size_t)len);
+            rp2[r + 1] = rp2[r] + len;
+        }
+        EncodeParams q = p;
+        q.sigma = 0;
+        std::string err = encode_csr(m, n, nnz, rp2.data(), c2.data(), v2.data(), dtype, q, c, dev);
+        if (!err.empty()) return err;
+        c.sigma = p.sigma;
+        c.perm = std::move(perm);
+        return "";
+    }
     const int threads = thread_count(p.threads);
     // checks in row chunks; the error reported is the one a serial scan finds
     // first (the lowest failing row)
@@ -687,6 +713,7 @@ std::string save_container(const Container &c, const std::string &path) {
     const size_t o_w = sz; sz = al8(sz + 4 * c.words.size());
     const size_t o_ed = sz; sz = al8(sz + 4 * c.escd.size());
     const size_t o_ev = sz; sz = al8(sz + vb * c.escv.size());
+    const size_t o_pm = sz; sz = al8(sz + (c.sigma ? 4 * (size_t)c.m : 0));
     std::vector<uint8_t> b(sz, 0);
     put_table(b, o_dt, c.dtab);
     put_table(b, o_vt, c.vtab);
@@ -700,6 +727,7 @@ std::string save_container(const Container &c, const std::string &path) {
         if (vb == 8) memcpy(&b[o_ev + 8 * i], &c.escv[i], 8);
         else { uint32_t x = (uint32_t)c.escv[i]; memcpy(&b[o_ev + 4 * i], &x, 4); }
     }
+    if (c.sigma && c.m) memcpy(&b[o_pm], c.perm.data(), 4 * (size_t)c.m);
     memcpy(&b[0], "CSRDTANS", 8);
     uint32_t h32[4] = {1, c.dtype, c.layout, c.lane_nnz};
     memcpy(&b[8], h32, 16);
@@ -709,6 +737,7 @@ std::string save_container(const Container &c, const std::string &path) {
     memcpy(&b[88], &c.seed, 8);
     memcpy(&b[104], &c.first_mode, 4);
     memcpy(&b[108], &c.esc_mode, 4);
+    memcpy(&b[112], &c.sigma, 4);
     uint64_t chk = fnv1a(b.data() + kHeader, sz - kHeader);
     memcpy(&b[96], &chk, 8);
     FILE *f = fopen(path.c_str(), "wb");
@@ -749,9 +778,11 @@ std::string load_container(const std::string &path, Container &c) {
     memcpy(&c.seed, &b[88], 8);
     memcpy(&c.first_mode, &b[104], 4);
     memcpy(&c.esc_mode, &b[108], 4);
+    memcpy(&c.sigma, &b[112], 4);
     if (c.dtype != kF32 && c.dtype != kF64) return fail("ECORRUPT", "bad dtype");
     if (c.first_mode > 1) return fail("ECORRUPT", "bad first-delta mode");
     if (c.esc_mode > 1 || (c.esc_mode == 1 && (nd != 0 || nv != 0))) return fail("ECORRUPT", "bad escape mode");
+    if (c.sigma % kWave || (c.sigma && c.layout != kLayoutRow)) return fail("ECORRUPT", "bad row-sort window");
     if (c.layout != kLayoutRow && c.layout != kLayoutNnz) return fail("ECORRUPT", "bad layout");
     if (c.m < 0 || c.n < 0 || c.nnz < 0 || nw < 0 || nd < 0 || nv < 0 || c.m >= (1ll << 31) ||
         c.n >= (1ll << 31) || c.nnz >= (1ll << 31))
@@ -770,6 +801,7 @@ std::string load_container(const std::string &path, Container &c) {
     const size_t o_w = sz; sz = al8(sz + 4 * (size_t)nw);
     const size_t o_ed = sz; sz = al8(sz + 4 * (size_t)nd);
     const size_t o_ev = sz; sz = al8(sz + vb * (size_t)nv);
+    const size_t o_pm = sz; sz = al8(sz + (c.sigma ? 4 * (size_t)c.m : 0));
     if (sz != b.size()) return fail("ECORRUPT", "file size does not match the header");
     std::string e = get_table(&b[o_dt], c.dtab, true);
     if (e.empty()) e = get_table(&b[o_vt], c.vtab, false, c.dtype == kF32 ? 32 : 64);
@@ -801,6 +833,15 @@ std::string load_container(const std::string &path, Container &c) {
     for (int64_t i = 0; i < nv; ++i) {
         if (vb == 8) memcpy(&c.escv[i], &b[o_ev + 8 * i], 8);
         else { uint32_t x; memcpy(&x, &b[o_ev + 4 * i], 4); c.escv[i] = x; }
+    }
+    if (c.sigma) {
+        // the stored order must be the sorted order of the original rows
+        c.perm.resize(c.m);
+        if (c.m) memcpy(c.perm.data(), &b[o_pm], 4 * (size_t)c.m);
+        std::vector<int32_t> orp, chk;
+        if (!original_row_ptr(c, orp)) return fail("ECORRUPT", "row order is not a permutation");
+        sigma_order(c.m, orp.data(), c.sigma, chk);
+        if (chk != c.perm) return fail("ECORRUPT", "rows are not in sorted order");
     }
     return "";
 }

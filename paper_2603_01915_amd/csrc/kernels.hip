@@ -831,6 +831,11 @@ struct LaneGeo {
     int32_t krow;  // layout NNZ: index of `row` in the nonempty-row list
     int32_t row, row_beg, row_end;
     int2 n1, n2;
+    // layout ROW: the row of the original matrix this lane's row is (rows
+    // sorted within windows are encoded in that order) and the position of
+    // its first nonzero there
+    int32_t orow;
+    int64_t gout;
 };
 
 template <int LAYOUT>
@@ -843,7 +848,7 @@ __device__ __forceinline__ int32_t lane_first_row(const DevMat &a, int64_t slice
 template <int LAYOUT>
 __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint32_t lane,
                                             int32_t first) {
-    LaneGeo q{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0)};
+    LaneGeo q{0, 0, 0, 0, 0, 0, make_int2(0, 0), make_int2(0, 0), 0, 0};
     const int64_t l = slice * kWave + lane;
     if constexpr (LAYOUT == 1) {
         // the row's bounds only (lanes past the last row read the last
@@ -853,6 +858,12 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
         q.row = first;
         q.row_beg = a.row_ptr[lc];
         q.row_end = a.row_ptr[lc + 1];
+        q.orow = first;
+        q.gout = q.row_beg;
+        if (a.row_perm) {  // uniform
+            q.orow = a.row_perm[lc];
+            q.gout = a.orig_row_ptr[q.orow];
+        }
     } else if (l < a.num_lanes) {
         q.g0 = l * (int64_t)a.lane_nnz;
         q.cnt = (int)min((int64_t)a.lane_nnz, a.nnz - q.g0);
@@ -903,7 +914,11 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
     const int cnt = LAYOUT == 1 ? (live ? geo.row_end - geo.row_beg : 0) : geo.cnt;
     int32_t row = geo.row, row_beg = geo.row_beg, row_end = geo.row_end, krow = geo.krow;
     int2 n1 = geo.n1, n2 = geo.n2;
-    Sink sink(sp, l, row, LAYOUT == 2 && row_beg < g0);
+    // the sink sees rows and nonzero positions of the original matrix (row
+    // layout: rows may be encoded in another order); the decoder's own row
+    // (first deltas) is the encoded one
+    const int32_t srow = LAYOUT == 1 ? geo.orow : row;
+    Sink sink(sp, l, srow, LAYOUT == 2 && row_beg < g0);
     const uint32_t scale = Sink::col_scale(sp);  // column deltas arrive multiplied by it
     const int S = (cnt + 3) >> 2;
     const int F = min(S - 1, cnt >> 2);  // steps j < F: four nonzeros and a next segment
@@ -932,7 +947,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
     }
     const uint32_t pf = src.prefetch(pos, lane);
     uint32_t d = 0, r = 1, col = first_base(a.first_mode, (uint32_t)row) * scale;
-    int64_t g = g0;
+    int64_t g = LAYOUT == 1 ? geo.gout : g0;
 
     auto step = [&](auto fullc, int j) {
         constexpr bool FULL = decltype(fullc)::value;
@@ -1063,7 +1078,7 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
             for (int k = 0; k < 4; ++k) {
                 col += dl[k];
                 cols[k] = col;
-                rowk[k] = row;
+                rowk[k] = srow;
             }
             sink.template segment<false>(cols, v, nreal, g, rowk);
         } else {
@@ -1105,8 +1120,8 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
     cur.vpos = vpos;
     if constexpr (LAYOUT == 1) {
         // (a cooperative sink needs every lane of the wavefront)
-        if constexpr (Sink::kCoop) sink.finish_lane(row, kComplete, live && l < a.m);
-        else if (live && l < a.m) sink.finish_row(row, kComplete);
+        if constexpr (Sink::kCoop) sink.finish_lane(srow, kComplete, live && l < a.m);
+        else if (live && l < a.m) sink.finish_row(srow, kComplete);
     } else {
         // `row` holds this lane's last nonzeros: complete when it ends here;
         // started in an earlier lane, a head when it ends here, else a

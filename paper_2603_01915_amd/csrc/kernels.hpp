@@ -36,6 +36,10 @@ struct DevMat {
     int32_t no_escape;         // 1: neither table holds the escape symbol
     uint32_t first_mode;       // first delta of a row: 0 its column, 1 relative to the row
     int32_t esc_in_stream;     // 1: escaped symbols sit in the word stream (else escd / escv)
+    // layout ROW with rows sorted within windows (else null): the original
+    // row of every encoded row, and the original matrix's row pointers
+    const int32_t *row_perm;
+    const int32_t *orig_row_ptr;
 };
 
 struct Launch {

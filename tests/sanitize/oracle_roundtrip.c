@@ -9,7 +9,7 @@
 
 int oracle_encode(const char *path, int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                   const int32_t *col, const void *vals, int dtype, int layout, int lane_nnz,
-                  uint64_t seed, int first_mode, int esc_mode);
+                  uint64_t seed, int first_mode, int esc_mode, int sigma);
 int oracle_decode(const char *path, int32_t *row_ptr_out, int32_t *col_out, void *vals_out);
 
 static uint64_t state = 99;
@@ -46,7 +46,7 @@ static int one(const char *path, int64_t m, int64_t n, int maxlen, int pool, int
         rp[i + 1] = (int32_t)nnz;
     }
     const void *vals = dtype == 2 ? (const void *)v : (const void *)f;
-    int bad = oracle_encode(path, m, n, nnz, rp, ci, vals, dtype, layout, T, rnd(), first, esc);
+    int bad = oracle_encode(path, m, n, nnz, rp, ci, vals, dtype, layout, T, rnd(), first, esc, layout == 1 ? 64 * (esc + first) : 0);
     int32_t *rp2 = malloc((m + 1) * sizeof(int32_t));
     int32_t *ci2 = malloc((nnz + 1) * sizeof(int32_t));
     double *v2 = malloc((nnz + 1) * sizeof(double));

@@ -160,3 +160,19 @@ def test_batch_full():
     B.spmv(xd, yd, alpha=0.75, beta=-1.5)
     for (m, c), x, y, yy in zip(mats, xs, yd, y0):
         check_spmv(y.cpu().numpy(), c[0], c[1], c[2], x, yy, 0.75, -1.5, np.float32)
+
+
+@pytest.mark.parametrize("layout,sigma", [("row", 0), ("row", 1024), ("nnz", 0)])
+def test_skewed_full(layout, sigma):
+    """The skewed-rows workload (2^21 rows, heavy-tailed lengths up to 512) in
+    the encodings its bench lines time: rows in CSR order, rows sorted within
+    windows of 1024, and the nonzero layout."""
+    torch = need_gpu()
+    progress("skewed rows full size %s sigma=%d" % (layout, sigma))
+    rp, ci, v = workloads.skewed_rows()
+    n = len(rp) - 1
+    A = P.Matrix.from_csr(rp, ci, v, n, layout=layout, sort_window=sigma)
+    assert A.info()["sort_window"] == sigma
+    assert decode_equal(torch, A, rp, ci, v)
+    x = workloads.vector(n, 6)
+    check_spmv(A.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), rp, ci, v, x, None, 1, 0, np.float64)

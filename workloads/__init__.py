@@ -23,6 +23,11 @@ tests can run the same recipe at small sizes.
      index), CSR over rows.
   4b. batch: 64 square matrices with round(2^(10+6u)) rows, 8..64 columns per
      row within +-512 of the diagonal, a 64-value float pool per matrix.
+  6. skewed rows: 2^21 x 2^21, row lengths 1 + floor(6 * Lomax(1.3)) capped
+     at 512 (a heavy tail around a mean near 20), columns uniform within
+     +-32768 of the diagonal, duplicates merged, values from a pool of 256
+     distinct N(0,1) doubles: the irregular-but-not-power-law rows a sorted
+     (SELL-C-sigma) base is meant for.
   5. graph models for the delta-entropy study: Erdős–Rényi G(n, d/(n-1)),
      Watts–Strogatz (k neighbours, rewiring 0.1), Barabási–Albert (m links
      per new node), as symmetric patterns.
@@ -220,6 +225,18 @@ def batch(count: int = 64, seed: int = 1005, lo_exp: int = 10, hi_exp: int = 16,
         vals = pool[rng.integers(0, 64, size=len(cols))]
         out.append((m, _to_csr(m, rows, cols, vals)))
     return out
+
+
+# ---------------------------------------------------------------- config 6
+def skewed_rows(m: int = 1 << 21, half: int = 32768, cap: int = 512, seed: int = 1006) -> CSR:
+    rng = np.random.default_rng(seed)
+    lengths = np.minimum(cap, 1 + np.floor(6 * rng.pareto(1.3, size=m))).astype(np.int64)
+    rows = np.repeat(np.arange(m, dtype=np.int64), lengths)
+    cols = np.clip(rows + rng.integers(-half, half + 1, size=len(rows)), 0, m - 1)
+    key = np.unique(rows * m + cols)  # sorted by (row, col), duplicates merged
+    rows, cols = key // m, key % m
+    pool = _distinct_normal_pool(rng, 256, np.float64)
+    return _to_csr(m, rows, cols, pool[rng.integers(0, 256, size=len(cols))])
 
 
 # ---------------------------------------------------------------------------
