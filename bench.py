@@ -247,8 +247,8 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload == "batch":
-        return bench_batch(args, torch, P)
+    if args.workload.startswith("batch"):
+        return bench_batch(args, torch, P, int(args.workload[len("batch"):] or 1))
     if args.workload == "autograd":
         return bench_autograd(args, torch, P)
     if args.workload == "encode":
@@ -619,9 +619,10 @@ def bench_sym(args, torch, P):
     return 0
 
 
-def bench_batch(args, torch, P):
+def bench_batch(args, torch, P, k=1):
     """64 banded FP32 matrices of 1k-64k rows (8-64 nonzeros per row) in one
-    persistent launch, against the plain CSR kernel launched per matrix."""
+    persistent launch (k right-hand sides per matrix: one launch per column
+    chunk), against the plain CSR kernel launched per matrix."""
     import workloads
 
     log("generating 64 uneven matrices")
@@ -633,7 +634,7 @@ def bench_batch(args, torch, P):
     enc_s = time.perf_counter() - t0
     dt_bytes = sum(A.info()["total_bytes"] for A in enc)
     csr_bytes = sum(A.info()["csr_bytes"] for A in enc)
-    vec_bytes = sum(2 * m * 4 for m, _ in mats_csr)
+    vec_bytes = sum(2 * m * 4 * k for m, _ in mats_csr)
     copies = args.copies or max(1, math.ceil(2 * MALL_BYTES / (dt_bytes + vec_bytes)))
     sets = [enc]
     if copies > 1:
@@ -651,25 +652,30 @@ def bench_batch(args, torch, P):
             A.to_device()
     batches = [P.Batch(S) for S in sets]
     gen = torch.Generator(device="cuda").manual_seed(2005)
-    xs = [[torch.rand(m, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
+    shp = (lambda m: (m,)) if k == 1 else (lambda m: (m, k))
+    xs = [[torch.rand(shp(m), dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
           for _ in range(copies)]
-    ys = [[torch.empty(m, dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(copies)]
+    ys = [[torch.empty(shp(m), dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(copies)]
 
     def step(i):
         j = i % copies
-        batches[j].spmv(xs[j], ys[j])
+        if k == 1:
+            batches[j].spmv(xs[j], ys[j])
+        else:
+            batches[j].spmm(xs[j], ys[j])
 
     log("timing %d steps over %d copies" % (args.steps, copies))
     ms, _ = time_steps(torch, step, args.steps, args.warmup)
-    flops = 2.0 * total_nnz
+    flops = 2.0 * total_nnz * k
     alg = dt_bytes + vec_bytes
     res = {
         "metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 6),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded generator)",
-        "config": {"workload": "batch of 64 banded fp32 matrices, 1k-64k rows, 8-64 nnz/row, one launch",
-                   "matrices": len(mats_csr), "nnz": total_nnz, "k": 1, "layout": "row",
+        "config": {"workload": "batch of 64 banded fp32 matrices, 1k-64k rows, 8-64 nnz/row, one launch"
+                               + ("" if k == 1 else " per column chunk, k=%d" % k),
+                   "matrices": len(mats_csr), "nnz": total_nnz, "k": k, "layout": "row",
                    "copies_rotated": copies},
         "compressed_GBps": round(alg / (ms * 1e-3) / 1e9, 2),
         "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBPS,
@@ -683,14 +689,17 @@ def bench_batch(args, torch, P):
         log("plain CSR baseline, one launch per matrix")
         ccopies = max(1, math.ceil(2 * MALL_BYTES / (csr_bytes + vec_bytes)))
         cs = [[P.CsrBaseline(c[0], c[1], c[2], m) for m, c in mats_csr] for _ in range(ccopies)]
-        cx = [[torch.rand(m, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
+        cx = [[torch.rand(shp(m), dtype=torch.float32, device="cuda", generator=gen) * 2 - 1 for m, _ in mats_csr]
               for _ in range(ccopies)]
-        cy = [[torch.empty(m, dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(ccopies)]
+        cy = [[torch.empty(shp(m), dtype=torch.float32, device="cuda") for m, _ in mats_csr] for _ in range(ccopies)]
 
         def cstep(i):
             j = i % ccopies
             for B, x, y in zip(cs[j], cx[j], cy[j]):
-                B.spmv(x, y)
+                if k == 1:
+                    B.spmv(x, y)
+                else:
+                    B.spmm(x, y)
 
         cms, _ = time_steps(torch, cstep, args.steps, args.warmup)
         res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),

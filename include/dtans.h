@@ -18,7 +18,8 @@
  *     (borrowed).  "device" pointers are HIP device allocations owned by the
  *     caller (e.g. torch tensor data_ptr()); the library never frees them.
  *   - Product calls (dtans_spmv, dtans_spmm, dtans_spmm_t, dtans_spmv_sym,
- *     dtans_decode_csr, dtans_batch_spmv, dtans_csr_spmv, dtans_csr_spmm)
+ *     dtans_decode_csr, dtans_batch_spmv, dtans_batch_spmm, dtans_csr_spmv,
+ *     dtans_csr_spmm)
  *     are asynchronous on the caller's HIP stream (NULL = the null stream),
  *     allocate nothing and never synchronize.  They need the matrix on the
  *     current device with scratch for their number of right-hand sides:
@@ -293,6 +294,16 @@ dtans_status dtans_decode_csr(dtans_matrix *mat, int32_t *row_ptr, int32_t *col_
  */
 dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_batch **out);
 dtans_status dtans_batch_spmv(dtans_batch *batch, const void *const *xs, void *const *ys,
+                              double alpha, double beta, void *stream);
+/* Y_i = alpha * A_i X_i + beta * Y_i for every matrix of the batch with k >= 1
+ * right-hand sides: Xs[i] (device, n_i x k) and Ys[i] (device, m_i x k) are
+ * row major with leading dimension k.  Each launch decodes every matrix once
+ * for a chunk of columns: 32 / 16 / 8 FP32 or 16 / 8 / 4 FP64 columns by
+ * lane groups sharing 16-byte pieces of the rows of X (when every X_i and
+ * Y_i is 16-byte aligned and k * sizeof(value) is a multiple of 16), the
+ * rest 4, 2 or 1 at a time (the multi-vector product of Sec. IV-B over the
+ * multi-matrix launch).  Same stream rule as dtans_batch_spmv. */
+dtans_status dtans_batch_spmm(dtans_batch *batch, int32_t k, const void *const *Xs, void *const *Ys,
                               double alpha, double beta, void *stream);
 void dtans_batch_destroy(dtans_batch *batch);
 

@@ -504,6 +504,33 @@ class Batch:
                                             ctypes.c_void_p(_stream(stream))))
         return ys
 
+    def spmm(self, Xs, Ys=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """Y_i = alpha * A_i X_i + beta * Y_i with X_i [n_i, k], Y_i [m_i, k]
+        contiguous (the same k for every matrix)."""
+        torch = _torch()
+        if len(Xs) != len(self.matrices):
+            raise ValueError("one X per matrix")
+        k = Xs[0].size(1) if Xs and Xs[0].dim() == 2 else 0
+        if Ys is None:
+            Ys = [torch.empty((m.shape[0], k), dtype=m.torch_dtype, device=X.device)
+                  for m, X in zip(self.matrices, Xs)]
+            beta = 0.0
+        for m, X, Y in zip(self.matrices, Xs, Ys):
+            _dev(X, m.torch_dtype, "X", 2)
+            _dev(Y, m.torch_dtype, "Y", 2)
+            if tuple(X.shape) != (m.shape[1], k) or tuple(Y.shape) != (m.shape[0], k):
+                raise ValueError("X_i must be [n_i, k] and Y_i [m_i, k] with one k")
+            if X.stride(0) != k or Y.stride(0) != k:
+                raise ValueError("X_i and Y_i must be contiguous")
+        if k == 0:
+            return Ys
+        cnt = len(self.matrices)
+        xa = (ctypes.c_void_p * cnt)(*[X.data_ptr() for X in Xs])
+        ya = (ctypes.c_void_p * cnt)(*[Y.data_ptr() for Y in Ys])
+        _lib.check(self._L.dtans_batch_spmm(self._h, k, xa, ya, alpha, beta,
+                                            ctypes.c_void_p(_stream(stream))))
+        return Ys
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.dtans_batch_destroy(self._h)

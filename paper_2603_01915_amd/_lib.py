@@ -85,6 +85,7 @@ SIGNATURES = {
     "dtans_decode_csr": (_I32, [_P, _P, _P, _P, _P]),
     "dtans_batch_create": (_I32, [_I32, _PP, _PP]),
     "dtans_batch_spmv": (_I32, [_P, _PP, _PP, _D, _D, _P]),
+    "dtans_batch_spmm": (_I32, [_P, _I32, _PP, _PP, _D, _D, _P]),
     "dtans_batch_destroy": (None, [_P]),
     "dtans_csr_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, ctypes.c_int, _I32, _PP]),
     "dtans_csr_spmv": (_I32, [_P, _P, _P, _D, _D, _P]),

@@ -989,6 +989,28 @@ dtans_status dtans_batch_spmv(dtans_batch *b, const void *const *xs, void *const
     return DTANS_OK;
 }
 
+dtans_status dtans_batch_spmm(dtans_batch *b, int32_t k, const void *const *Xs, void *const *Ys, double alpha,
+                              double beta, void *stream) {
+    if (!b || !Xs || !Ys) return set_err(DTANS_EINVAL, "null argument");
+    if (k < 1) return set_err(DTANS_EINVAL, "k must be at least 1");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cnt = b->mats.size();
+    const size_t vb = b->f64 ? 8 : 4;
+    BatchPtrs ptrs{};
+    bool aligned = (k * vb) % 16 == 0;
+    for (size_t i = 0; i < cnt; ++i) {
+        const Container &c = b->mats[i]->c;
+        if ((c.m > 0 && !Ys[i]) || (c.nnz > 0 && !Xs[i])) return set_err(DTANS_EINVAL, "null matrix in batch");
+        if (c.n * (int64_t)k * (int64_t)vb > (1ll << 32)) aligned = false;  // 32-bit byte offsets
+        if ((uintptr_t)Xs[i] % 16 || (uintptr_t)Ys[i] % 16) aligned = false;
+        ptrs.xs[i] = Xs[i];
+        ptrs.ys[i] = Ys[i];
+    }
+    hipError_t e = launch_batch_spmm(b->dev, ptrs, (int)cnt, b->f64, k, aligned, alpha, beta, b->launch, st);
+    if (e != hipSuccess) return hip_err(e, "dtans_batch_spmm launch");
+    return DTANS_OK;
+}
+
 void dtans_batch_destroy(dtans_batch *b) { delete b; }
 
 // -------------------------------------------------------------- CSR baseline

@@ -1529,6 +1529,39 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
     }
 }
 
+// The same launch for k right-hand sides: X_i is n_i x k and Y_i m_i x k, row
+// major with leading dimension k; this launch takes the columns c0 .. c0 + KC
+// of every matrix (the sink's chunk), each matrix decoded once per launch.
+template <typename VT, class Sink, int MINW>
+__global__ __launch_bounds__(decode_max_threads(MINW), MINW) void batch_spmm_kernel(BatchDev b, int c0, int k,
+                                                                                     double alpha, double beta) {
+    __shared__ __align__(16) Tables<VT> tb;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), wpb = blockDim.x / kWave;
+    const int t0 = b.wg_task[blockIdx.x], t1 = b.wg_task[blockIdx.x + 1];
+    int cur = -1;
+    for (int t = t0; t < t1; ++t) {
+        const BatchTask task = b.tasks[t];
+        const DevMat a = b.mats[task.mat];
+        const int stage = task.mat == cur ? 0 : (cur < 0 ? 1 : 2);
+        cur = task.mat;
+        typename Sink::Params sp;
+        sp.X = (const VT *)b.ptrs[2 * task.mat] + c0;
+        sp.ldx = (uint32_t)k;
+        sp.Y = (VT *)b.ptrs[2 * task.mat + 1] + c0;
+        sp.ldy = (uint32_t)k;
+        sp.partial = nullptr;  // row layout: every row ends in its lane
+        sp.alpha = alpha;
+        sp.beta = beta;
+        const int64_t s0 = task.first_wave + wib, s_end = (int64_t)task.first_wave + task.num_waves;
+        const int64_t share = s0 < s_end ? (s_end - 1 - s0) / wpb + 1 : 0;
+        if (a.base_direct)
+            decode_rows<VT, Sink, 1>(a, tb, lane, sp, s_end, s0, wpb, share, stage);
+        else
+            decode_rows<VT, Sink, 0>(a, tb, lane, sp, s_end, s0, wpb, share, stage);
+    }
+}
+
 // ------------------------------------------------------- plain CSR
 // variant 1: G lanes per row (G a power of two <= 64), lanes of a group read
 // consecutive nonzeros; butterfly reduction inside the group.
@@ -2139,6 +2172,66 @@ hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, boo
     else
         hipLaunchKernelGGL(batch_kernel<float>, dim3(L.grid), block, 0, st, b, alpha, beta);
     return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t batch_spmm_impl(const BatchDev &b, int k, bool aligned, double alpha, double beta, Launch L,
+                           hipStream_t st) {
+    auto go = [&](auto kern, int c0) -> hipError_t {
+        // the task lists hold for any workgroup size; the kernel may allow fewer
+        // waves per workgroup than the plan (more registers per wave)
+        hipFuncAttributes fa;
+        int wpw = L.waves_per_wg;
+        if (hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess)
+            wpw = std::max(1, std::min(wpw, fa.maxThreadsPerBlock / 64));
+        hipLaunchKernelGGL(kern, dim3(L.grid), dim3(64 * wpw), 0, st, b, c0, k, alpha, beta);
+        return hipGetLastError();
+    };
+    constexpr int CL = 16 / (int)sizeof(VT);
+    int c0 = 0;
+    hipError_t e = hipSuccess;
+    // lane groups sharing each row of X (16-byte pieces), then single columns
+    while (aligned && e == hipSuccess && k - c0 >= 2 * CL) {
+        if (k - c0 >= 8 * CL) {
+            typedef CoopSpmmSink<VT, 8> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 8 * CL;
+        } else if (k - c0 >= 4 * CL) {
+            typedef CoopSpmmSink<VT, 4> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 4 * CL;
+        } else {
+            typedef CoopSpmmSink<VT, 2> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 2 * CL;
+        }
+    }
+    while (e == hipSuccess && c0 < k) {
+        if (k - c0 >= 4) {
+            typedef SpmmSink<VT, 4, false> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 4;
+        } else if (k - c0 >= 2) {
+            typedef SpmmSink<VT, 2, false> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 2;
+        } else {
+            typedef SpmmSink<VT, 1, false> S;
+            e = go(batch_spmm_kernel<VT, S, S::kOcc>, c0);
+            c0 += 1;
+        }
+    }
+    return e;
+}
+
+hipError_t launch_batch_spmm(const BatchDev &b, const BatchPtrs &ptrs, int count, bool f64, int k,
+                             bool aligned, double alpha, double beta, Launch L, hipStream_t st) {
+    hipLaunchKernelGGL(batch_ptrs_kernel, dim3(1), dim3(kMaxBatch), 0, st, ptrs, count,
+                       (void **)b.ptrs);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+    return f64 ? batch_spmm_impl<double>(b, k, aligned, alpha, beta, L, st)
+               : batch_spmm_impl<float>(b, k, aligned, alpha, beta, L, st);
 }
 
 hipError_t launch_flush(const void *buf, int64_t bytes, uint32_t *sink, hipStream_t st) {

@@ -109,6 +109,11 @@ struct BatchPtrs {
 // stay on one stream (the table is shared by its launches).
 hipError_t launch_batch(const BatchDev &b, const BatchPtrs &ptrs, int count, bool f64, double alpha,
                         double beta, Launch L, hipStream_t st);
+// k right-hand sides per matrix (X_i n_i x k, Y_i m_i x k, leading dimension
+// k); aligned: every X_i and Y_i starts 16-byte aligned and k * sizeof(value)
+// is a multiple of 16 (lane groups read 16-byte pieces of the rows of X)
+hipError_t launch_batch_spmm(const BatchDev &b, const BatchPtrs &ptrs, int count, bool f64, int k,
+                             bool aligned, double alpha, double beta, Launch L, hipStream_t st);
 
 // plain CSR baseline.  variant 1: G lanes per row; variant 2: lane_nnz
 // nonzeros per lane with partials + fix-up (lane_row, split_* as for DevMat).

@@ -162,6 +162,24 @@ def test_batch_full():
         check_spmv(y.cpu().numpy(), c[0], c[1], c[2], x, yy, 0.75, -1.5, np.float32)
 
 
+def test_batch_spmm_full():
+    """The 64-matrix batch with k = 8 right-hand sides per matrix: every
+    column of every Y_i against the oracle."""
+    torch = need_gpu()
+    progress("generating the 64-matrix batch (k = 8)")
+    mats = workloads.batch()
+    enc = [P.Matrix.from_csr(c[0], c[1], c[2], m, layout="row") for m, c in mats]
+    B = P.Batch(enc)
+    Xs = [workloads.vector(m, 300 + i, np.float32, k=8) for i, (m, _) in enumerate(mats)]
+    progress("batch spmm k = 8")
+    Ys = B.spmm([torch.from_numpy(X).cuda() for X in Xs])
+    for (m, c), X, Y in zip(mats, Xs, Ys):
+        Yref = oracle.spmm(c[0], c[1], c[2], X)
+        Yn = Y.cpu().numpy()
+        for j in range(8):
+            assert rel_error(Yn[:, j], Yref[:, j], oracle.absmv(c[0], c[1], c[2], X[:, j])) <= TOL[np.float32]
+
+
 @pytest.mark.parametrize("layout,sigma", [("row", 0), ("row", 1024), ("nnz", 0)])
 def test_skewed_full(layout, sigma):
     """The skewed-rows workload (2^21 rows, heavy-tailed lengths up to 512) in

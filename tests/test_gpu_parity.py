@@ -319,6 +319,50 @@ def test_batch_matches_single(dtype):
         check_spmv(y.cpu().numpy(), rp, ci, v, x, np.ones(len(rp) - 1, dtype), 2.0, -1.0, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("k", [1, 3, 8, 13, 32])
+def test_batch_spmm(dtype, k):
+    """Several right-hand sides per matrix in one batched launch per column
+    chunk: every column of every Y_i against the oracle, on 16-byte aligned
+    X_i / Y_i (lane-group chunks) and on views one element off (single
+    columns), with alpha and beta."""
+    torch = need_gpu()
+    mats = workloads.batch(count=12, lo_exp=6, hi_exp=12, half=64)
+    progress("batch spmm of %d %s k=%d" % (len(mats), dtype.__name__, k))
+    enc, Xs, refs = [], [], []
+    for i, (m, (rp, ci, v)) in enumerate(mats):
+        v = v.astype(dtype)
+        enc.append(P.Matrix.from_csr(rp, ci, v, m, layout="row"))
+        X = workloads.vector(m, 100 + i, dtype, k=k)
+        Xs.append(X)
+        refs.append((rp, ci, v))
+    b = P.Batch(enc)
+    Ys = b.spmm([torch.from_numpy(X).cuda() for X in Xs])
+    for (rp, ci, v), X, Y in zip(refs, Xs, Ys):
+        Yref = oracle.spmm(rp, ci, v, X)
+        Yn = Y.cpu().numpy()
+        for c in range(k):
+            assert rel_error(Yn[:, c], Yref[:, c], oracle.absmv(rp, ci, v, X[:, c])) <= TOL[dtype], c
+    # unaligned storage (one element into a buffer), alpha and beta
+    Xo, Yo, Y0 = [], [], []
+    for (m, _), X in zip(mats, Xs):
+        bx = torch.zeros(m * k + 1, dtype=enc[0].torch_dtype, device="cuda")
+        bx[1:] = torch.from_numpy(X).cuda().reshape(-1)
+        Xo.append(bx[1:].view(m, k))
+        y0 = workloads.vector(m, 7, dtype, k=k)
+        by = torch.zeros(m * k + 1, dtype=enc[0].torch_dtype, device="cuda")
+        by[1:] = torch.from_numpy(y0).cuda().reshape(-1)
+        Yo.append(by[1:].view(m, k))
+        Y0.append(y0)
+    b.spmm(Xo, Yo, alpha=0.5, beta=-1.0)
+    for (rp, ci, v), X, Y, y0 in zip(refs, Xs, Yo, Y0):
+        Yref = oracle.spmm(rp, ci, v, X, y0, alpha=0.5, beta=-1.0)
+        Yn = Y.cpu().numpy()
+        for c in range(k):
+            scale = 0.5 * oracle.absmv(rp, ci, v, X[:, c]) + np.abs(y0[:, c].astype(np.float64))
+            assert rel_error(Yn[:, c], Yref[:, c], scale) <= TOL[dtype], c
+
+
 def test_empty_and_degenerate():
     torch = need_gpu()
     for layout, T in LAYOUTS:

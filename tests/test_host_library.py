@@ -33,7 +33,7 @@ def test_header_symbols_exported():
     names = set(re.findall(
         r"^\s*(?:dtans_status|void|const char \*|int64_t|int32_t)\s*\*?\s*(dtans_\w+)\s*\(",
         text, re.M))
-    assert len(names) == 33
+    assert len(names) == 34
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for n in sorted(names):
         assert hasattr(lib, n), n
