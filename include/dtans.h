@@ -221,9 +221,16 @@ dtans_status dtans_spmv(dtans_matrix *mat, const void *x, void *y, double alpha,
                         void *stream);
 
 /*
- * Multi-vector product Y = alpha * A X + beta * Y, decoding each stream once
- * for all k right-hand sides.  X is n x k row-major with leading dimension
- * ldx >= k; Y is m x k row-major with ldy >= k (device pointers).
+ * Multi-vector product Y = alpha * A X + beta * Y (Sec. IV-B: the decoded
+ * nonzeros are used for all right-hand sides while decoding).  X is n x k
+ * row-major with leading dimension ldx >= k; Y is m x k row-major with
+ * ldy >= k (device pointers).  Every stream is decoded once per column chunk:
+ * chunks of 32 / 16 / 8 FP32 or 16 / 8 / 4 FP64 columns, whose rows of X lane
+ * groups read as 16-byte pieces, when X is 16-byte aligned, ldx * sizeof(value)
+ * a multiple of 16 and n * ldx * sizeof(value) <= 2^32 (so k = 32 FP32 is one
+ * decode); the remaining columns (or all of them otherwise) in chunks of at
+ * most 16 FP32 / 8 FP64 columns read per lane.  dtans_reserve(k) sizes the
+ * partial sums of rows split over lanes.
  */
 dtans_status dtans_spmm(dtans_matrix *mat, int32_t k, const void *X, int64_t ldx, void *Y,
                         int64_t ldy, double alpha, double beta, void *stream);
