@@ -240,10 +240,29 @@ struct SpmmSink {
             // common case, taken by the whole wavefront or not at all (a
             // uniform branch): no lane has a tail or a row end here
             if (!ballot(!(nreal >= 4 && (!MULTI || rowk[3] == cur)))) {
+                if constexpr (UNIT && KC == 1 && sizeof(VT) == 8) {
+                    // FP64 vector: when nonzeros k and k+1 of every lane are
+                    // adjacent columns (uniform tests), one 16-byte load gives
+                    // both x values.  The address unit takes such a load of a
+                    // wavefront in the cycles of one 8-byte load (stencil and
+                    // banded rows have runs of adjacent columns).
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                    for (int k = 0; k < 4; k += 2) {
+                        if (!ballot(col[k + 1] != col[k] + 8u)) {
+                            const uint4 q = *(const uint4 *)((const char *)p.X + col[k]);
+                            x[k][0] = __builtin_bit_cast(VT, (uint64_t)q.y << 32 | q.x);
+                            x[k + 1][0] = __builtin_bit_cast(VT, (uint64_t)q.w << 32 | q.z);
+                        } else {
+                            x[k][0] = xrow(col[k])[0];
+                            x[k + 1][0] = xrow(col[k + 1])[0];
+                        }
+                    }
+                } else {
 #pragma unroll
-                    for (int c = 0; c < KC; ++c) x[k][c] = xrow(col[k])[c];
+                    for (int k = 0; k < 4; ++k)
+#pragma unroll
+                        for (int c = 0; c < KC; ++c) x[k][c] = xrow(col[k])[c];
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
 #pragma unroll
