@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
+    ap.add_argument("--no-paper-form", action="store_true",
+                    help="stencil: skip the extra timing of the paper's own format")
     ap.add_argument("--no-warm", action="store_true", help="skip the single-copy (warm) timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (counter calibration)")
@@ -383,6 +385,36 @@ def main():
         res["speedup_vs_rocsparse"] = round(rms / ms, 3)
         for B_ in Rs:
             B_.close()
+    if args.workload == "stencil" and not args.no_paper_form and not args.first_delta_column and not args.max_mult:
+        # the same product in the paper's own format: first delta = column,
+        # multiplicity cap M = 256 (general tables)
+        log("paper-form encoding")
+        A1 = P.Matrix.from_csr(rp, ci, v, n, layout=args.layout, lane_nnz=args.lane_nnz,
+                               first_delta_column=True, max_mult=256)
+        inf1 = A1.info()
+        per1 = inf1["total_bytes"] + vec_bytes
+        c1 = max(1, math.ceil(2 * MALL_BYTES / per1))
+        ms1 = [A1]
+        if c1 > 1:
+            import tempfile
+
+            with tempfile.TemporaryDirectory() as td:
+                path = os.path.join(td, "p.dtans")
+                A1.save(path)
+                ms1 += [P.Matrix.load(path) for _ in range(c1 - 1)]
+        for M_ in ms1:
+            M_.to_device().reserve(k)
+        x1 = [xs[i % copies] for i in range(c1)]
+        y1 = [torch.empty(shape_y, dtype=tdt, device="cuda") for _ in range(c1)]
+        pms, _ = time_steps(torch, lambda i: ms1[i % c1].spmv(x1[i % c1], y1[i % c1]), args.steps, args.warmup)
+        ab1 = inf1["total_bytes"] + vec_bytes
+        res["paper_form"] = {"ms": round(pms, 6), "GFLOP/s": round(flops / (pms * 1e-3) / 1e9, 3),
+                             "frac": round(ab1 / (pms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                             "bits_per_nnz": round(inf1["bits_per_nnz"], 3),
+                             "escaped_deltas": inf1["esc_delta"], "direct_table": bool(inf1["direct_table"]),
+                             "first_delta": "column", "max_mult": 256, "copies_rotated": c1}
+        if "csr_baseline" in res:
+            res["paper_form"]["speedup_vs_csr"] = round(res["csr_baseline"]["ms"] / pms, 3)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
@@ -630,7 +662,7 @@ def bench_batch(args, torch, P, k=1):
     total_nnz = sum(len(c[1]) for _, c in mats_csr)
     log("encoding %d matrices, %d nonzeros" % (len(mats_csr), total_nnz))
     t0 = time.perf_counter()
-    enc = [P.Matrix.from_csr(c[0], c[1], c[2], m, layout="row") for m, c in mats_csr]
+    enc = [P.Matrix.from_csr(c[0], c[1], c[2], m, layout="row", sort_window=args.sort_window) for m, c in mats_csr]
     enc_s = time.perf_counter() - t0
     dt_bytes = sum(A.info()["total_bytes"] for A in enc)
     csr_bytes = sum(A.info()["csr_bytes"] for A in enc)
@@ -705,6 +737,38 @@ def bench_batch(args, torch, P, k=1):
         res["csr_baseline"] = {"ms": round(cms, 6), "GFLOP/s": round(flops / (cms * 1e-3) / 1e9, 3),
                                "copies_rotated": ccopies, "launches_per_step": len(mats_csr)}
         res["speedup_vs_csr"] = round(cms / ms, 3)
+        del cs, cx, cy
+        # one launch for all matrices: the block-diagonal CSR matrix of the
+        # batch (rows and columns of matrix i offset by those before it), x
+        # and y the matrices' vectors laid end to end
+        log("plain CSR baseline, one launch (block diagonal)")
+        import numpy as np
+
+        offs = np.cumsum([0] + [m for m, _ in mats_csr])
+        lens = np.concatenate([np.diff(c[0]) for _, c in mats_csr])
+        rp_all = np.zeros(len(lens) + 1, np.int64)
+        np.cumsum(lens, out=rp_all[1:])
+        ci_all = np.concatenate([c[1].astype(np.int64) + offs[i] for i, (_, c) in enumerate(mats_csr)])
+        v_all = np.concatenate([c[2] for _, c in mats_csr])
+        ntot = int(offs[-1])
+        one = [P.CsrBaseline(rp_all.astype(np.int32), ci_all.astype(np.int32), v_all, ntot)
+               for _ in range(ccopies)]
+        ox = [torch.rand(shp(ntot), dtype=torch.float32, device="cuda", generator=gen) * 2 - 1
+              for _ in range(ccopies)]
+        oy = [torch.empty(shp(ntot), dtype=torch.float32, device="cuda") for _ in range(ccopies)]
+
+        def ostep(i):
+            j = i % ccopies
+            if k == 1:
+                one[j].spmv(ox[j], oy[j])
+            else:
+                one[j].spmm(ox[j], oy[j])
+
+        oms, _ = time_steps(torch, ostep, args.steps, args.warmup)
+        res["csr_one_launch_baseline"] = {"ms": round(oms, 6), "GFLOP/s": round(flops / (oms * 1e-3) / 1e9, 3),
+                                          "copies_rotated": ccopies,
+                                          "note": "block-diagonal CSR of the 64 matrices, one launch"}
+        res["speedup_vs_csr_one_launch"] = round(oms / ms, 3)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -103,8 +103,8 @@ typedef struct {
                               order), so a wave's 64 lanes get rows of similar
                               length; the order is stored and every product and
                               dtans_decode_csr work in the original row order.
-                              dtans_encode_csr only; batches and dtans_spmv_sym
-                              return DTANS_EUNSUPPORTED for such matrices */
+                              dtans_encode_csr only; dtans_spmv_sym returns
+                              DTANS_EUNSUPPORTED for such matrices */
     int32_t reserved0;
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;

@@ -901,8 +901,6 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
         if ((mats[i]->c.dtype == kF64) != f64) return set_err(DTANS_EINVAL, "batch matrices must share a dtype");
         if (mats[i]->c.layout != kLayoutRow)
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must use the ROW layout");
-        if (mats[i]->c.sigma)
-            return set_err(DTANS_EUNSUPPORTED, "batch matrices must keep their rows in CSR order");
         if (mats[i]->c.n * (int64_t)mats[i]->c.value_bytes() > (1ll << 32))
             return set_err(DTANS_EUNSUPPORTED, "batch matrices must have x of at most 4 GiB");
         dtans_status s = reserve(mats[i], 1, nullptr);
@@ -930,7 +928,9 @@ dtans_status dtans_batch_create(int32_t count, dtans_matrix *const *mats, dtans_
     int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)mats[0]->num_cus * wgcu,
                                                            (total_waves + wpw - 1) / wpw));
     // contiguous ranges of about equal cost, one per workgroup, each split
-    // into per-matrix tasks
+    // into per-matrix tasks (measured: cutting the ranges at matrix
+    // boundaries instead, so that no workgroup restages its tables, is
+    // slower)
     std::vector<double> prefix(total_waves + 1, 0.0);
     for (int64_t i = 0; i < total_waves; ++i) prefix[i + 1] = prefix[i] + cost[i];
     b->wg_task.push_back(0);

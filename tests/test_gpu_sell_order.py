@@ -1,8 +1,9 @@
 """GPU parity of row-sorted (SELL-C-sigma base) containers: every product and
 the decode work in the original row order, within the oracle's tolerance
 (SpMV, SpMM through both the per-lane and the lane-group sinks, the
-transposed product on both of its paths, both stream stages), bit-exact for
-decoding; batches and the symmetric product refuse such matrices."""
+transposed product on both of its paths, both stream stages, the
+multi-matrix launch), bit-exact for decoding; the symmetric product refuses
+such matrices."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -99,13 +100,35 @@ def test_sorted_ring_stage_and_oracle_container(tmp_path, dtype):
     check_spmv(B.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
 
 
-def test_sorted_refused_by_batch_and_symmetric():
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sorted_in_batch(dtype):
+    """Row-sorted matrices in the multi-matrix launch (k = 1 and k = 8)."""
+    torch = need_gpu()
+    mats = workloads.batch(count=10, lo_exp=6, hi_exp=12, half=64)
+    progress("sorted rows in a batch %s" % dtype.__name__)
+    enc, refs = [], []
+    for i, (m, (rp, ci, v)) in enumerate(mats):
+        v = v.astype(dtype)
+        enc.append(P.Matrix.from_csr(rp, ci, v, m, layout="row", sort_window=64 * (1 + i % 3)))
+        refs.append((rp, ci, v))
+    b = P.Batch(enc)
+    xs = [workloads.vector(m, 100 + i, dtype) for i, (m, _) in enumerate(mats)]
+    ys = b.spmv([torch.from_numpy(x).cuda() for x in xs])
+    for (rp, ci, v), x, y in zip(refs, xs, ys):
+        check_spmv(y.cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+    Xs = [workloads.vector(m, 200 + i, dtype, k=8) for i, (m, _) in enumerate(mats)]
+    Ys = b.spmm([torch.from_numpy(X).cuda() for X in Xs])
+    for (rp, ci, v), X, Y in zip(refs, Xs, Ys):
+        Yref = oracle.spmm(rp, ci, v, X)
+        Yn = Y.cpu().numpy()
+        for c in range(8):
+            assert rel_error(Yn[:, c], Yref[:, c], oracle.absmv(rp, ci, v, X[:, c])) <= TOL[dtype]
+
+
+def test_sorted_refused_by_symmetric():
     torch = need_gpu()
     rp, ci, v = workloads.stencil27(6)
-    progress("sorted rows refused")
-    A = P.Matrix.from_csr(rp, ci, v, 6 ** 3, sort_window=64)
-    with pytest.raises(P.DtansError):
-        P.Batch([A])
+    progress("sorted rows refused by the symmetric product")
     rpu, ciu, vu, diag = P.symmetric_split(rp, ci, v)
     H = P.Matrix.from_csr(rpu, ciu, vu, 6 ** 3, sort_window=64)
     x = torch.from_numpy(workloads.vector(6 ** 3, 1, np.float64)).cuda()
