@@ -117,6 +117,8 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 template <typename VT, int KC, bool UNIT, typename ACC = double, int DEFER = 0>
 struct SpmmSink {
     static constexpr bool kCoop = false;
+    // paired x loads (see segment); the general-table decoder runs without them
+    static constexpr bool kPairs = UNIT && KC == 1 && sizeof(VT) == 8;
     static_assert(!DEFER || KC <= 4, "deferred products keep 4*KC x values in registers");
     static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
     struct Params {
@@ -206,7 +208,7 @@ struct SpmmSink {
 #pragma unroll
         for (int c = 0; c < KC; ++c) acc[c] = (ACC)0;
     }
-    template <bool MULTI>
+    template <bool MULTI, bool PAIRS = kPairs>
     __device__ __forceinline__ void segment(const uint32_t col[4], const VT v[4], int nreal,
                                             int64_t, const int32_t rowk[4]) {
         if constexpr (DEFER) {
@@ -240,7 +242,7 @@ struct SpmmSink {
             // common case, taken by the whole wavefront or not at all (a
             // uniform branch): no lane has a tail or a row end here
             if (!ballot(!(nreal >= 4 && (!MULTI || rowk[3] == cur)))) {
-                if constexpr (UNIT && KC == 1 && sizeof(VT) == 8) {
+                if constexpr (PAIRS) {
                     // FP64 vector: when nonzeros k and k+1 of every lane are
                     // adjacent columns (uniform tests), one 16-byte load gives
                     // both x values.  The address unit takes such a load of a
@@ -395,6 +397,7 @@ __device__ __forceinline__ T lane_value_of(T v, uint32_t src) {
 template <typename VT, int G, typename ACC = double>
 struct CoopSpmmSink {
     static constexpr bool kCoop = true;
+    static constexpr bool kPairs = false;
     static constexpr int CL = 16 / (int)sizeof(VT), KC = G * CL, NG = kWave / G;
     // waves per SIMD to allow: with eight slots per lane the accumulators and
     // the rows of X in flight do not fit beside the decoder in 128 registers;
@@ -570,6 +573,7 @@ struct CoopSpmmSink {
 template <typename VT, int KC>
 struct TransSink {
     static constexpr bool kCoop = false;
+    static constexpr bool kPairs = false;
     static constexpr int kOcc = KC <= 2 ? 8 : 4;
     struct Params {
         const VT *dY;
@@ -619,6 +623,7 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 5); 
 template <typename VT, int KC>
 struct TransLdsSink {
     static constexpr bool kCoop = false;
+    static constexpr bool kPairs = false;
     static constexpr int kOcc = 4;
     struct Params {
         const VT *dY;
@@ -656,6 +661,7 @@ struct TransLdsSink {
 template <typename VT>
 struct DecodeSink {
     static constexpr bool kCoop = false;
+    static constexpr bool kPairs = false;
     static constexpr int kOcc = 8;
     struct Params {
         int32_t *col;
@@ -1099,7 +1105,9 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
                 cols[k] = col;
                 rowk[k] = srow;
             }
-            sink.template segment<false>(cols, v, nreal, g, rowk);
+            // (the general-table decoder measured slower with paired loads)
+            if constexpr (Sink::kPairs && TF == 0) sink.template segment<false, false>(cols, v, nreal, g, rowk);
+            else sink.template segment<false>(cols, v, nreal, g, rowk);
         } else {
             // resolve row boundaries first: a column delta restarts at every
             // row; a nonzero at the end of the current row starts the next
