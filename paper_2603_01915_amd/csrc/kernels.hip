@@ -1422,12 +1422,15 @@ __device__ __forceinline__ int64_t first_run_start(int32_t a) { return ((int64_t
 template <typename VT>
 __global__ __launch_bounds__(256) void fixup_kernel(SplitRows sr, const double *partial, int KC,
                                                     int runs, VT *Y, int64_t ldy, double alpha,
-                                                    double beta) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= sr.n) return;
+                                                    double beta, int log_tpr) {
+    // 2^log_tpr >= KC threads per split row, one column each (consecutive
+    // threads read consecutive doubles of a partial slot)
+    const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> log_tpr;
+    const int c = (int)(threadIdx.x & ((1u << log_tpr) - 1));
+    if (s >= sr.n || c >= KC) return;
     const int32_t a = sr.first[s], b = sr.last[s];
     if (b - a > (runs ? kLongSplitRuns : kLongSplit)) return;
-    for (int c = 0; c < KC; ++c) {
+    {
         const double *head = partial + c;  // head slot of lane l: head[2 * l * KC]
         double sum = partial[(2 * (int64_t)a + 1) * KC + c];
         if (runs) {
@@ -1486,8 +1489,11 @@ hipError_t launch_fixup(const SplitRows &sr, const double *partial, int KC, int 
                         int64_t ldy, double alpha, double beta, hipStream_t st) {
     if (sr.n == 0) return hipSuccess;
     if (KC > kMaxFixupCols) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((sr.n + 255) / 256)), dim3(256), 0, st, sr,
-                       partial, KC, runs, Y, ldy, alpha, beta);
+    int lt = 0;
+    while ((1 << lt) < KC) ++lt;
+    const int64_t threads = sr.n << lt;
+    hipLaunchKernelGGL(fixup_kernel<VT>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, sr,
+                       partial, KC, runs, Y, ldy, alpha, beta, lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sr.n_long == 0) return e;
     hipLaunchKernelGGL(fixup_long_kernel<VT>, dim3((unsigned)((sr.n_long + 3) / 4)), dim3(256), 0, st,
