@@ -135,3 +135,42 @@ def test_sorted_refused_by_symmetric():
     with pytest.raises(P.DtansError):
         H.spmv_sym(x, torch.from_numpy(diag).cuda())
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_sorted_with_in_stream_escapes_and_edges(dtype):
+    """Sorted rows and in-stream escapes together, on a matrix whose row
+    count is not a multiple of the window, with empty rows and fewer rows
+    than a wave at the end; single products, SpMM and the product for callers
+    that cannot allocate."""
+    torch = need_gpu()
+    rng = np.random.default_rng(12)
+    m, n = 64 * 5 + 37, 900
+    lens = rng.choice([0, 0, 1, 3, 7, 20, 60], size=m)
+    rows = [np.sort(rng.choice(n, size=k, replace=False)) for k in lens]
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate(rows).astype(np.int32)
+    v = rng.standard_normal(len(ci)).astype(dtype)  # distinct values: escapes
+    rp = rp.astype(np.int32)
+    progress("sorted rows + in-stream escapes %s" % dtype.__name__)
+    A = P.Matrix.from_csr(rp, ci, v, n, sort_window=128, escape_in_stream=True)
+    inf = A.info()
+    assert inf["sort_window"] == 128 and inf["escape_in_stream"] == 1
+    _, c2, v2 = A.decode_csr()
+    torch.cuda.synchronize()
+    assert np.array_equal(c2.cpu().numpy(), ci)
+    assert np.array_equal(v2.cpu().numpy().view(np.uint8), v.view(np.uint8))
+    x = workloads.vector(n, 3, dtype)
+    check_spmv(A.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), rp, ci, v, x, None, 1.0, 0.0, dtype)
+    X = workloads.vector(n, 4, dtype, k=16)
+    Xd = torch.from_numpy(X).cuda()
+    Y = A.spmm(Xd)
+    Yref = oracle.spmm(rp, ci, v, X)
+    Yn = Y.cpu().numpy()
+    for c in range(16):
+        assert rel_error(Yn[:, c], Yref[:, c], oracle.absmv(rp, ci, v, X[:, c])) <= TOL[dtype]
+    Y2 = torch.empty_like(Y)
+    A.spmm_noalloc(Xd, Y2)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, Y2)
