@@ -103,8 +103,9 @@ typedef struct {
                               order), so a wave's 64 lanes get rows of similar
                               length; the order is stored and every product and
                               dtans_decode_csr work in the original row order.
-                              dtans_encode_csr only; dtans_spmv_sym returns
-                              DTANS_EUNSUPPORTED for such matrices */
+                              dtans_encode_csr and dtans_encode_csr_gpu (the rows
+                              are permuted on the host first); dtans_encode_csr_device
+                              and dtans_spmv_sym return DTANS_EUNSUPPORTED */
     int32_t reserved0;
     uint64_t perm_seed;    /* seed of the random slot permutation (Sec. IV-F) */
 } dtans_encode_opts;

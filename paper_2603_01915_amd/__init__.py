@@ -168,7 +168,8 @@ class Matrix:
     @classmethod
     def from_csr_device(cls, row_ptr, col, vals, n: int, layout="auto", lane_nnz: int = 0,
                         waves_per_wg: int = 0, wg_per_cu: int = 0, seed: int = 1, stream_stage: int = 0,
-                        max_mult: int = 0, first_delta_column: bool = False, stream=None) -> "Matrix":
+                        max_mult: int = 0, first_delta_column: bool = False, escape_in_stream: bool = False,
+                        sort_window: int = 0, stream=None) -> "Matrix":
         """Encode CSR arrays already in device memory: contiguous 1-D CUDA
         tensors, row_ptr and col int32, vals float32 or float64.  The passes
         over the nonzeros run on the GPU (on `stream`, default the current
@@ -185,7 +186,7 @@ class Matrix:
             raise ValueError("col and vals must have nnz entries, row_ptr m + 1")
         L = _lib.load()
         o = _encode_opts(L, layout, lane_nnz, waves_per_wg, wg_per_cu, False, seed, stream_stage, max_mult,
-                         first_delta_column)
+                         first_delta_column, escape_in_stream, sort_window)
         code = _lib.F64 if vals.dtype == torch.float64 else _lib.F32
         h = ctypes.c_void_p()
         _lib.check(L.dtans_encode_csr_device(row_ptr.numel() - 1, n, col.numel(), row_ptr.data_ptr(),

@@ -391,7 +391,8 @@ std::string encode_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr
         // sorted rows: encode the row-permuted matrix, keep the order
         if (p.layout != kLayoutRow || p.sigma % kWave)
             return fail("EINVAL", "a row-sort window needs the ROW layout and a multiple of 64 rows");
-        if (dev) return fail("EUNSUPPORTED", "the device encoder keeps rows in CSR order");
+        if (dev && dev->inputs_on_device())
+            return fail("EUNSUPPORTED", "rows of device-resident arrays are encoded in CSR order");
         for (int64_t i = 0; i < m; ++i)
             if (row_ptr[i + 1] < row_ptr[i]) return fail("EINVAL", "row_ptr decreases at row " + std::to_string(i));
         std::vector<int32_t> perm, rp2(m + 1), c2(nnz);

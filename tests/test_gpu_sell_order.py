@@ -174,3 +174,23 @@ def test_sorted_with_in_stream_escapes_and_edges(dtype):
     A.spmm_noalloc(Xd, Y2)
     torch.cuda.synchronize()
     assert torch.equal(Y, Y2)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_sorted_gpu_encoder_same_container(tmp_path, dtype):
+    """The GPU encoder (host arrays in) writes the same sorted-row container,
+    byte for byte, as the host encoder; device-resident arrays are refused."""
+    torch = need_gpu()
+    name, rp, ci, v, n = CASES[1]
+    v = v.astype(dtype)
+    progress("sorted rows, GPU encoder %s" % dtype.__name__)
+    A = P.Matrix.from_csr(rp, ci, v, n, sort_window=256)
+    B = P.Matrix.from_csr(rp, ci, v, n, sort_window=256, gpu_encode=True)
+    pa, pb = str(tmp_path / "a.dtans"), str(tmp_path / "b.dtans")
+    A.save(pa)
+    B.save(pb)
+    assert open(pa, "rb").read() == open(pb, "rb").read()
+    d = [torch.from_numpy(t).cuda() for t in (rp, ci, v)]
+    with pytest.raises(P.DtansError):
+        P.Matrix.from_csr_device(d[0], d[1], d[2], n, sort_window=256)
+    torch.cuda.synchronize()
