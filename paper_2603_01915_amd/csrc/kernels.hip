@@ -128,6 +128,9 @@ struct SpmmSink {
         uint32_t ldy;
         double *partial;  // [lane][head/tail][KC]
         double alpha, beta;
+        // x holds at least two values: the short segments of single-row
+        // lanes may then read x in 16-byte pairs too (see segment)
+        uint32_t pair_x = 0;
     };
     const Params p;
     int64_t lane;
@@ -275,6 +278,42 @@ struct SpmmSink {
                 // single-row lanes: only a lane's last segment is short (or it
                 // has none left); column 0 stands in for the missing nonzeros,
                 // whose products are dropped by a select, with no branches
+                if constexpr (PAIRS) {
+                    // Pairs as in the common case when both pairs of every
+                    // lane holding them are adjacent (a uniform test) and x
+                    // holds at least two values.  A lane holding both
+                    // nonzeros of a pair reads them at the first column; a
+                    // lane holding only the first reads the 16 bytes that end
+                    // at its column (or start at column 0), a lane holding
+                    // neither reads columns 0 and 1: every read stays inside
+                    // x.
+                    if (p.pair_x && !ballot((1 < nreal && col[1] != col[0] + 8u) ||
+                                            (3 < nreal && col[3] != col[2] + 8u))) {
+                        bool up[2];
+                        uint4 q[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int k = 2 * h;
+                            const bool one = k < nreal, both = k + 1 < nreal;
+                            up[h] = one && !both && col[k] != 0u;
+                            const uint32_t off = both ? col[k] : (up[h] ? col[k] - 8u : 0u);
+                            q[h] = *(const uint4 *)((const char *)p.X + off);
+                        }
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const VT lo = __builtin_bit_cast(VT, (uint64_t)q[h].y << 32 | q[h].x);
+                            const VT hi = __builtin_bit_cast(VT, (uint64_t)q[h].w << 32 | q[h].z);
+                            x[2 * h][0] = up[h] ? hi : lo;
+                            x[2 * h + 1][0] = hi;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const ACC t = fma((ACC)v[k], (ACC)x[k][0], acc[0]);
+                            acc[0] = k < nreal ? t : acc[0];
+                        }
+                        return;
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t cc = k < nreal ? col[k] : 0u;
@@ -1552,6 +1591,7 @@ __global__ __launch_bounds__(1024, 7) void batch_kernel(BatchDev b, double alpha
         sp.partial = nullptr;
         sp.alpha = alpha;
         sp.beta = beta;
+        sp.pair_x = a.n >= 2;
         // this wavefront's waves of the task: first_wave + wib, + wpb, ...
         const int64_t s0 = task.first_wave + wib, s_end = (int64_t)task.first_wave + task.num_waves;
         const int64_t share = s0 < s_end ? (s_end - 1 - s0) / wpb + 1 : 0;
@@ -1956,6 +1996,7 @@ hipError_t spmm_impl(const DevMat &a, int k, const VT *X, int64_t ldx, VT *Y, in
         sp.partial = partial;
         sp.alpha = alpha;
         sp.beta = beta;
+        sp.pair_x = a.n >= 2;
         constexpr int occ = SinkT::kOcc, occn = occ_nnz(SinkT::kOcc);
         hipError_t e =
             a.layout == 1
