@@ -254,7 +254,13 @@ struct SpmmSink {
 #pragma unroll
                     for (int k = 0; k < 4; k += 2) {
                         if (!ballot(col[k + 1] != col[k] + 8u)) {
-                            const uint4 q = *(const uint4 *)((const char *)p.X + col[k]);
+                            // (an offset the compiler cannot share with the
+                            // other branch: a shared address would be formed
+                            // as a 64-bit pointer ahead of the branch, where
+                            // this form keeps the base in SGPRs)
+                            uint32_t o = col[k];
+                            asm("" : "+v"(o));
+                            const uint4 q = *(const uint4 *)((const char *)p.X + o);
                             x[k][0] = __builtin_bit_cast(VT, (uint64_t)q.y << 32 | q.x);
                             x[k + 1][0] = __builtin_bit_cast(VT, (uint64_t)q.w << 32 | q.z);
                         } else {
