@@ -119,6 +119,7 @@ struct SpmmSink {
     static constexpr bool kCoop = false;
     // paired x loads (see segment); the general-table decoder runs without them
     static constexpr bool kPairs = UNIT && KC == 1 && sizeof(VT) == 8;
+    static constexpr bool kPairs32 = UNIT && KC == 1 && sizeof(VT) == 4;  // per-lane pairs
     static_assert(!DEFER || KC <= 4, "deferred products keep 4*KC x values in registers");
     static constexpr int kOcc = KC <= 2 ? 8 : 4;  // waves per SIMD to allow
     struct Params {
@@ -267,6 +268,41 @@ struct SpmmSink {
                             x[k][0] = xrow(col[k])[0];
                             x[k + 1][0] = xrow(col[k + 1])[0];
                         }
+                    }
+                } else if constexpr (kPairs32) {
+                    // FP32 vector, pairs per lane: an 8-byte load ending at
+                    // column k+1 gives x at k+1 and, in the lanes whose
+                    // columns k and k+1 are adjacent, x at k too; only the
+                    // other lanes load x at k on their own, so the address
+                    // unit sees their cache lines only (half the lanes of a
+                    // weight pruned to half its entries).  The load starts at
+                    // column 0 when column k+1 is 0 (repeated columns), so it
+                    // stays inside x once x holds two values.
+                    // (every load is issued before any value is selected,
+                    // so that no wait comes between them)
+                    if (p.pair_x) {  // uniform
+                        uint2 q[2];
+                        VT xs[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const uint32_t c1 = col[2 * h + 1];
+                            q[h] = *(const uint2 *)((const char *)p.X + (c1 >= 4u ? c1 - 4u : 0u));
+                        }
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            xs[h] = (VT)0;
+                            if (col[2 * h] + 4u != col[2 * h + 1]) xs[h] = xrow(col[2 * h])[0];
+                        }
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const uint32_t c1 = col[2 * h + 1];
+                            const VT lo = __builtin_bit_cast(VT, q[h].x), hi = __builtin_bit_cast(VT, q[h].y);
+                            x[2 * h + 1][0] = c1 >= 4u ? hi : lo;
+                            x[2 * h][0] = col[2 * h] + 4u == c1 ? lo : xs[h];
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) x[k][0] = xrow(col[k])[0];
                     }
                 } else {
 #pragma unroll
