@@ -129,8 +129,9 @@ struct SpmmSink {
         uint32_t ldy;
         double *partial;  // [lane][head/tail][KC]
         double alpha, beta;
-        // x holds at least two values: the short segments of single-row
-        // lanes may then read x in 16-byte pairs too (see segment)
+        // x holds at least two values, so that a read of two adjacent values
+        // starting at column 0 stays inside it (the FP64 short segments and
+        // the FP32 per-lane pairs in segment); 0 turns those reads off
         uint32_t pair_x = 0;
     };
     const Params p;
