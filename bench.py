@@ -201,7 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="stencil",
-                    help="stencil, band, rmat, pruned1, pruned8, pruned32, batch, autograd, encode or sym")
+                    help="stencil, band, rmat, skewed, pruned1, pruned8, pruned32, batch, batch8, "
+                         "autograd, encode or sym")
     ap.add_argument("--layout", default="auto")
     ap.add_argument("--lane-nnz", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
