@@ -48,6 +48,24 @@ __device__ __forceinline__ T uniform_load(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
 }
 
+// Pointers into global memory for the decoder's loads.  A pointer the kernel
+// read from device memory (the per-matrix views of the multi-matrix launches)
+// is generic to the compiler, which then reads through it with flat
+// instructions: 64-bit addresses, and counted against the LDS wait counter
+// too, so that every wait for a table lookup would also wait for the gathers
+// and stream words in flight.  Loads through these pointers are global loads
+// whatever the pointer's origin (every matrix and vector is a device
+// allocation).
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+using gmut = __attribute__((address_space(1))) T *;
+// (the declared alignment is what the addresses guarantee: a load declared
+// more aligned than its address lets the compiler draw wrong conclusions)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));                // 16-byte aligned
+typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));  // 16 bytes, 8-byte aligned
+typedef uint64_t u64_a4 __attribute__((aligned(4)));                        // 8 bytes, 4-byte aligned
+
 template <typename VT> struct Bits;
 template <> struct Bits<double> { typedef uint64_t T; };
 template <> struct Bits<float> { typedef uint32_t T; };
@@ -195,12 +213,12 @@ struct SpmmSink {
     static __device__ __forceinline__ uint32_t col_scale(const Params &) {
         return UNIT ? (uint32_t)sizeof(VT) : 1u;
     }
-    __device__ __forceinline__ const VT *xrow(uint32_t col) const {
-        return UNIT ? (const VT *)((const char *)p.X + col) : p.X + (uint64_t)col * p.ldx;
+    __device__ __forceinline__ gptr<VT> xrow(uint32_t col) const {
+        return UNIT ? (gptr<VT>)((const char *)p.X + col) : (gptr<VT>)(p.X + (uint64_t)col * p.ldx);
     }
     __device__ __forceinline__ void store(int32_t row, int kind) {
         if (kind == kComplete) {
-            VT *y = UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy;
+            const gmut<VT> y = (gmut<VT>)(UNIT ? p.Y + row : p.Y + (uint64_t)(uint32_t)row * p.ldy);
 #pragma unroll
             for (int c = 0; c < KC; ++c)
                 y[c] = (VT)(p.beta == 0.0 ? p.alpha * (double)acc[c]
@@ -262,7 +280,7 @@ struct SpmmSink {
                             // this form keeps the base in SGPRs)
                             uint32_t o = col[k];
                             asm("" : "+v"(o));
-                            const uint4 q = *(const uint4 *)((const char *)p.X + o);
+                            const u32x4_a8 q = *(gptr<u32x4_a8>)((const char *)p.X + o);
                             x[k][0] = __builtin_bit_cast(VT, (uint64_t)q.y << 32 | q.x);
                             x[k + 1][0] = __builtin_bit_cast(VT, (uint64_t)q.w << 32 | q.z);
                         } else {
@@ -282,12 +300,12 @@ struct SpmmSink {
                     // (every load is issued before any value is selected,
                     // so that no wait comes between them)
                     if (p.pair_x) {  // uniform
-                        uint2 q[2];
+                        uint64_t q[2];
                         VT xs[2];
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
                             const uint32_t c1 = col[2 * h + 1];
-                            q[h] = *(const uint2 *)((const char *)p.X + (c1 >= 4u ? c1 - 4u : 0u));
+                            q[h] = *(gptr<u64_a4>)((const char *)p.X + (c1 >= 4u ? c1 - 4u : 0u));
                         }
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
@@ -297,7 +315,8 @@ struct SpmmSink {
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
                             const uint32_t c1 = col[2 * h + 1];
-                            const VT lo = __builtin_bit_cast(VT, q[h].x), hi = __builtin_bit_cast(VT, q[h].y);
+                            const VT lo = __builtin_bit_cast(VT, (uint32_t)q[h]);
+                            const VT hi = __builtin_bit_cast(VT, (uint32_t)(q[h] >> 32));
                             x[2 * h + 1][0] = c1 >= 4u ? hi : lo;
                             x[2 * h][0] = col[2 * h] + 4u == c1 ? lo : xs[h];
                         }
@@ -333,14 +352,14 @@ struct SpmmSink {
                     if (p.pair_x && !ballot((1 < nreal && col[1] != col[0] + 8u) ||
                                             (3 < nreal && col[3] != col[2] + 8u))) {
                         bool up[2];
-                        uint4 q[2];
+                        u32x4_a8 q[2];
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
                             const int k = 2 * h;
                             const bool one = k < nreal, both = k + 1 < nreal;
                             up[h] = one && !both && col[k] != 0u;
                             const uint32_t off = both ? col[k] : (up[h] ? col[k] - 8u : 0u);
-                            q[h] = *(const uint4 *)((const char *)p.X + off);
+                            q[h] = *(gptr<u32x4_a8>)((const char *)p.X + off);
                         }
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
@@ -785,18 +804,18 @@ struct GlobalWords {
     // would otherwise fold into the lane count)
     __device__ __forceinline__ uint32_t read(uint32_t pos, uint64_t mask) const {
         const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
-        return *(const uint32_t *)(W + (p + 4 * lane_prefix(mask)));
+        return *(gptr<uint32_t>)(W + (p + 4 * lane_prefix(mask)));
     }
     // the same when every lane of the wavefront reads (prefix = lane)
     __device__ __forceinline__ uint32_t read_lanes(uint32_t pos, uint32_t lane) const {
         const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
-        return *(const uint32_t *)(W + (p + 4 * lane));
+        return *(gptr<uint32_t>)(W + (p + 4 * lane));
     }
     // the word at byte offset pos (uniform) + off (per lane): escapes stored
     // in the stream
     __device__ __forceinline__ uint32_t word_at(uint32_t pos, uint32_t off) const {
         const uint32_t p = __builtin_amdgcn_readfirstlane(pos);
-        return *(const uint32_t *)(W + (p + off));
+        return *(gptr<uint32_t>)(W + (p + off));
     }
     // Nothing in the memory system fetches a stream ahead of its reads, so
     // every step's words would come from HBM.  Once the first words are
@@ -806,7 +825,7 @@ struct GlobalWords {
     // complete in order, so the steps' own waits already cover it.
     __device__ __forceinline__ uint32_t prefetch(uint32_t pos, uint32_t lane) const {
         const uint32_t o = (pos & ~127u) + 128u * (lane + 1);
-        return o < bytes ? *(const uint32_t *)(W + o) : 0u;
+        return o < bytes ? *(gptr<uint32_t>)(W + o) : 0u;
     }
     __device__ __forceinline__ void retire(uint32_t v) const { asm volatile("" ::"v"(v)); }
     __device__ __forceinline__ void step_begin() {}
@@ -963,13 +982,13 @@ __device__ __forceinline__ LaneGeo lane_geo(const DevMat &a, int64_t slice, uint
         // loading the next one's geometry does not wait for it
         const int64_t lc = l < a.num_lanes ? l : a.num_lanes - 1;
         q.row = first;
-        q.row_beg = a.row_ptr[lc];
-        q.row_end = a.row_ptr[lc + 1];
+        q.row_beg = ((gptr<int32_t>)a.row_ptr)[lc];
+        q.row_end = ((gptr<int32_t>)a.row_ptr)[lc + 1];
         q.orow = first;
         q.gout = q.row_beg;
         if (a.row_perm) {  // uniform
-            q.orow = a.row_perm[lc];
-            q.gout = a.orig_row_ptr[q.orow];
+            q.orow = ((gptr<int32_t>)a.row_perm)[lc];
+            q.gout = ((gptr<int32_t>)a.orig_row_ptr)[q.orow];
         }
     } else if (l < a.num_lanes) {
         q.g0 = l * (int64_t)a.lane_nnz;
@@ -1115,14 +1134,14 @@ __device__ __forceinline__ void decode_slice(const DevMat &a, const Tables<VT> &
                     for (int k = 0; k < 4; ++k) {
                         const bool f = act && k < rem && (int32_t)md[k] < 0;
                         const uint64_t mk = ballot(f);
-                        if (f) dl[k] = ED[dpos + lane_prefix(mk)] * scale;
+                        if (f) dl[k] = ((gptr<uint32_t>)ED)[dpos + lane_prefix(mk)] * scale;
                         dpos += (uint32_t)__popcll(mk);
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const bool f = act && k < rem && (int32_t)mv[k] < 0;
                         const uint64_t mk = ballot(f);
-                        if (f) v[k] = EV[vpos + lane_prefix(mk)];
+                        if (f) v[k] = ((gptr<VT>)EV)[vpos + lane_prefix(mk)];
                         vpos += (uint32_t)__popcll(mk);
                     }
                 }
@@ -1262,15 +1281,15 @@ template <typename VT>
 __device__ __forceinline__ void stage_tables(const DevMat &a, Tables<VT> &tb, uint32_t scale) {
     constexpr int kV = kSlots * (int)sizeof(VEntry<VT>) / 16, kT = kSlots * 8 / 16;
     constexpr int kAll = kV + kT, kU = 4;  // pieces per thread and pass
-    const uint4 *gv = (const uint4 *)a.tabval, *gt = (const uint4 *)a.tab;
-    uint4 *lds = (uint4 *)&tb;  // tv, then td
+    const gptr<u32x4> gv = (gptr<u32x4>)a.tabval, gt = (gptr<u32x4>)a.tab;
+    u32x4 *lds = (u32x4 *)&tb;  // tv, then td
     const int nt = blockDim.x;
     for (int b = 0; b < kAll; b += kU * nt) {
-        uint4 t[kU];
+        u32x4 t[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int i = b + u * nt + (int)threadIdx.x;
-            t[u] = make_uint4(0, 0, 0, 0);
+            t[u] = u32x4{0u, 0u, 0u, 0u};
             if (i < kV) t[u] = gv[i];
             else if (i < kAll) {
                 t[u] = gt[i - kV];
